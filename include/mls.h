@@ -1,0 +1,150 @@
+/*
+ * mls.h -- C ABI of the MI355X (gfx950) moving-least-squares field library.
+ *
+ * The library evaluates the moving-least-squares (MLS) interpolation of
+ * Muelder et al., "A Moving Least Squares Based Approach for Contour
+ * Visualization of Multi-Dimensional Data" (Sec. 3.3), on every node of a
+ * 2-D grid laid over N scattered points that each carry D attribute values,
+ * and extracts contour lines of the resulting fields (Sec. 3.4).
+ *
+ * Per grid node p, with data points x_i and values f_i in R^D:
+ *   weights   w_i = w(|x_i - p|)         Gaussian exp(-r^2/h^2),
+ *                                         Wendland C2 (1-r/h)^4 (4r/h+1), r<h,
+ *                                         or inverse distance (r/h)^(-2 alpha)
+ *                                         (Eq. 4)
+ *   basis     b(u) = [1, u_x, u_y, u_x^2, u_x u_y, u_y^2]   (m = 1, 3, 6
+ *             terms for constant / linear / quadratic), u = (x_i - p) / h
+ *   normal equations   M c = R,  M = sum w_i b_i b_i^T,  R = sum w_i b_i f_i^T
+ *   value     field_d(p) = c_{0,d}
+ * The linear basis is the affine MLS of Eq. 6-8; the constant basis is the
+ * weighted mean of Eq. 5.  Where sum_i w_i < weight_floor the node is
+ * undetermined (NaN, degree code 255).  Otherwise a degree ladder runs: the
+ * requested degree is accepted if the equilibrated Cholesky factorisation of
+ * its normal matrix has every pivot >= pivot_tol, else the next lower degree
+ * is tried; degree 0 always succeeds.
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are device pointers (hipMalloc / torch CUDA tensors)
+ *    on the context's device; h_* are host pointers.  The caller owns every
+ *    buffer; the library never frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued asynchronously; results are valid after the stream syncs.
+ *  - Argument errors are detected before any device work is enqueued and
+ *    returned synchronously; nothing is written to outputs in that case.
+ *    A device failure during enqueue returns MLS_ERR_DEVICE.  The detail of
+ *    the last error of the calling thread is available from mls_last_error().
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MLS_H_
+#define MLS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLS_OK = 0,
+  MLS_ERR_INVALID_ARG = -1,   /* bad size, pointer, enum or parameter */
+  MLS_ERR_OUT_OF_MEMORY = -2, /* a library scratch allocation failed */
+  MLS_ERR_CAPACITY = -3,      /* output buffer too small (contour) */
+  MLS_ERR_DEVICE = -4,        /* HIP runtime error, wrong device */
+  MLS_ERR_UNSUPPORTED = -7    /* valid request this build does not run */
+} mls_status;
+
+typedef enum {
+  MLS_BASIS_CONSTANT = 0,  /* m = 1: weighted mean (Eq. 5) */
+  MLS_BASIS_LINEAR = 1,    /* m = 3: affine MLS (Eq. 6-8) */
+  MLS_BASIS_QUADRATIC = 2  /* m = 6 */
+} mls_basis;
+
+typedef enum {
+  MLS_W_GAUSSIAN = 0,    /* exp(-r^2/h^2) */
+  MLS_W_WENDLAND_C2 = 1, /* (1 - r/h)^4 (4 r/h + 1) for r < h, else 0 */
+  MLS_W_INVPOW = 2       /* (r/h)^(-2 alpha), Eq. 4 */
+} mls_weight_kind;
+
+/*
+ * Arithmetic of the weight x feature contraction (inputs and outputs are
+ * always float32; the per-node solve is always float64).
+ *  MLS_PREC_F64:  float64 contraction on the matrix cores.  This is the
+ *                 accurate plain path: the normal equations lose about
+ *                 log10(condition) digits, which float32 sums cannot spare.
+ */
+typedef enum {
+  MLS_PREC_F64 = 0
+} mls_precision;
+
+typedef struct {
+  int32_t kind;  /* mls_weight_kind */
+  double h;      /* bandwidth (Gaussian), support radius (Wendland), or length
+                    unit (inverse distance); finite and > 0 */
+  double alpha;  /* inverse-distance exponent (Eq. 4); ignored otherwise */
+} mls_weight;
+
+/* Node (r, c) sits at (x0 + c*dx, y0 + r*dy), 0 <= r < height,
+ * 0 <= c < width.  Fields are stored row-major [D][height][width]. */
+typedef struct {
+  double x0, y0, dx, dy;
+  int32_t width, height;
+} mls_grid;
+
+typedef struct {
+  double pivot_tol;     /* tau: smallest accepted equilibrated pivot; 1e-8 */
+  double weight_floor;  /* nodes with sum of weights below this are NaN; 1e-6 */
+} mls_solve_opts;
+
+typedef struct mls_context mls_context;
+
+/* Degree codes written to d_degree. */
+#define MLS_DEGREE_UNDETERMINED 255
+#define MLS_DEGREE_POINT_HIT 254
+
+/* Largest attribute count D accepted by mls_fit for each basis. */
+#define MLS_MAX_D_CONSTANT 255
+#define MLS_MAX_D_LINEAR 83
+#define MLS_MAX_D_QUADRATIC 40
+
+/* Status name ("MLS_OK", ...); never NULL. */
+const char* mls_status_string(mls_status s);
+
+/* Detail of the calling thread's last failed call ("" if none). */
+const char* mls_last_error(void);
+
+/* Create a context on HIP device `device` (must be a gfx950 device).
+ * Returns MLS_ERR_DEVICE if the device cannot be used. */
+mls_status mls_context_create(int32_t device, mls_context** out);
+
+/* Release a context and its scratch memory.  NULL is a no-op. */
+void mls_context_destroy(mls_context* ctx);
+
+/*
+ * Evaluate D MLS fields on a grid (Sec. 3.3, Eq. 4-8; see top of file).
+ *  d_points  float32 [n][2] (x, y), row-major, device
+ *  d_values  float32 [n][d], row-major, device
+ *  n >= 1 points, 1 <= d <= MLS_MAX_D_<basis> attributes
+ *  basis     mls_basis
+ *  weight    weight kind and parameters (host struct)
+ *  grid      grid description (host struct), width >= 1, height >= 1,
+ *            finite x0, y0, dx, dy
+ *  precision mls_precision of the contraction
+ *  opts      solve options (host struct) or NULL for the defaults
+ *  d_fields  float32 [d][height][width] output, device
+ *  d_degree  uint8 [height][width] output (accepted degree, 255 for
+ *            undetermined), device, or NULL
+ * Supported in this build: MLS_PREC_F64 with the Gaussian weight and all
+ * three bases; other combinations return MLS_ERR_UNSUPPORTED.
+ */
+mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
+                   int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                   const mls_grid* grid, int32_t precision,
+                   const mls_solve_opts* opts, float* d_fields, uint8_t* d_degree,
+                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLS_H_ */

@@ -1,0 +1,61 @@
+"""Loader of the in-tree HIP library (libmls_hip.so) and its C signatures.
+
+There is no fallback: if the library has not been built, or cannot be
+loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmls_hip.so")
+
+# Symbols declared in include/mls.h.
+EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
+           "mls_context_destroy", "mls_fit")
+
+
+class MlsGrid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class MlsWeight(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("h", ctypes.c_double),
+                ("alpha", ctypes.c_double)]
+
+
+class MlsSolveOpts(ctypes.Structure):
+    _fields_ = [("pivot_tol", ctypes.c_double), ("weight_floor", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmls_hip.so (raises if it is missing or broken)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run paper_1408_0677_amd/build.py "
+            "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.mls_status_string.argtypes = [ctypes.c_int]
+    lib.mls_status_string.restype = ctypes.c_char_p
+    lib.mls_last_error.argtypes = []
+    lib.mls_last_error.restype = ctypes.c_char_p
+    lib.mls_context_create.argtypes = [i32, ctypes.POINTER(P)]
+    lib.mls_context_create.restype = ctypes.c_int
+    lib.mls_context_destroy.argtypes = [P]
+    lib.mls_context_destroy.restype = None
+    lib.mls_fit.argtypes = [P, P, P, i64, i32, i32, ctypes.POINTER(MlsWeight),
+                            ctypes.POINTER(MlsGrid), i32,
+                            ctypes.POINTER(MlsSolveOpts), P, P, P]
+    lib.mls_fit.restype = ctypes.c_int
+    _lib = lib
+    return lib

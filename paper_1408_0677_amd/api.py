@@ -1,0 +1,118 @@
+"""Python binding of the C ABI in include/mls.h (argument marshalling only).
+
+Device memory and streams come from PyTorch: inputs and outputs are CUDA
+(HIP) tensors, the stream is torch's current stream unless one is passed.
+Every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+BASIS = {"constant": 0, "linear": 1, "quadratic": 2}
+WEIGHT = {"gaussian": 0, "wendland": 1, "invpow": 2}
+PRECISION = {"f64": 0}
+STATUS_OK = 0
+DEGREE_UNDETERMINED = 255
+
+
+class MlsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _lib.load()
+        name = lib.mls_status_string(status).decode()
+        detail = lib.mls_last_error().decode()
+        super().__init__(f"{where}: {name}: {detail}")
+        self.status = status
+        self.name = name
+
+
+def _check(status: int, where: str):
+    if status != STATUS_OK:
+        raise MlsError(status, where)
+
+
+class Context:
+    """An mls_context on one device (default: torch's current device)."""
+
+    def __init__(self, device: int | None = None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._ptr = ctypes.c_void_p()
+        _check(_lib.load().mls_context_create(self.device, ctypes.byref(self._ptr)),
+               "mls_context_create")
+
+    @property
+    def handle(self):
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            _lib.load().mls_context_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+def grid_struct(grid: dict) -> _lib.MlsGrid:
+    return _lib.MlsGrid(float(grid["x0"]), float(grid["y0"]), float(grid["dx"]),
+                        float(grid["dy"]), int(grid["width"]), int(grid["height"]))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussian",
+        h: float = 0.05, alpha: float = 1.0, precision: str = "f64",
+        pivot_tol: float = 1e-8, weight_floor: float = 1e-6, out=None,
+        degree_out=None, want_degree: bool = True, ctx: Context | None = None,
+        stream=None):
+    """MLS fields of ``values`` (N, D) at the nodes of ``grid``.
+
+    ``points`` float32 (N, 2) and ``values`` float32 (N, D) are contiguous
+    device tensors.  Returns ``(fields (D, H, W) float32, degree (H, W)
+    uint8 or None)``; ``out`` / ``degree_out`` may supply the buffers.
+    """
+    import torch
+    assert points.dtype == torch.float32 and values.dtype == torch.float32
+    assert points.is_contiguous() and values.is_contiguous()
+    if values.dim() == 1:
+        values = values.view(-1, 1)
+    n, d = values.shape
+    W, H = int(grid["width"]), int(grid["height"])
+    if out is None:
+        out = torch.empty((d, H, W), dtype=torch.float32, device=points.device)
+    if degree_out is None and want_degree:
+        degree_out = torch.empty((H, W), dtype=torch.uint8, device=points.device)
+    ctx = ctx or default_context(points.device.index)
+    g = grid_struct(grid)
+    wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
+    opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor))
+    st = _lib.load().mls_fit(ctx.handle, _ptr(points), _ptr(values), n, d, BASIS[basis],
+                             ctypes.byref(wt), ctypes.byref(g), PRECISION[precision],
+                             ctypes.byref(opts), _ptr(out), _ptr(degree_out),
+                             _stream_handle(stream))
+    _check(st, "mls_fit")
+    return out, degree_out

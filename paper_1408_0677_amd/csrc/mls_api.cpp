@@ -1,0 +1,184 @@
+// Host side of the C ABI (include/mls.h): argument validation, contexts,
+// dispatch to the kernels.  Every argument is checked before any HIP call,
+// so a rejected call has no side effect on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/mls.h"
+#include "mls_internal.h"
+
+struct mls_context {
+  int device;
+};
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+mls_status fail(mls_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+mls_status device_fail(hipError_t e, const char* where) {
+  return fail(MLS_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int max_d_for(int32_t basis) {
+  switch (basis) {
+    case MLS_BASIS_CONSTANT: return MLS_MAX_D_CONSTANT;
+    case MLS_BASIS_LINEAR: return MLS_MAX_D_LINEAR;
+    default: return MLS_MAX_D_QUADRATIC;
+  }
+}
+
+// Device pointers must belong to the context's device (or be managed).
+mls_status check_device_ptr(const mls_context* ctx, const void* ptr, const char* name) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MLS_ERR_INVALID_ARG, "%s is not a device pointer", name);
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(MLS_ERR_INVALID_ARG, "%s is not device memory", name);
+  if (attr.type == hipMemoryTypeDevice && attr.device != ctx->device)
+    return fail(MLS_ERR_INVALID_ARG, "%s lives on device %d, context is on %d", name,
+                attr.device, ctx->device);
+  return MLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mls_status_string(mls_status s) {
+  switch (s) {
+    case MLS_OK: return "MLS_OK";
+    case MLS_ERR_INVALID_ARG: return "MLS_ERR_INVALID_ARG";
+    case MLS_ERR_OUT_OF_MEMORY: return "MLS_ERR_OUT_OF_MEMORY";
+    case MLS_ERR_CAPACITY: return "MLS_ERR_CAPACITY";
+    case MLS_ERR_DEVICE: return "MLS_ERR_DEVICE";
+    case MLS_ERR_UNSUPPORTED: return "MLS_ERR_UNSUPPORTED";
+  }
+  return "MLS_UNKNOWN_STATUS";
+}
+
+const char* mls_last_error(void) { return g_last_error; }
+
+mls_status mls_context_create(int32_t device, mls_context** out) {
+  g_last_error[0] = '\0';
+  if (!out) return fail(MLS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return device_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= count)
+    return fail(MLS_ERR_DEVICE, "device %d out of range (%d devices)", device, count);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return device_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(MLS_ERR_DEVICE, "device %d is %s; this library is built for gfx950", device,
+                prop.gcnArchName);
+  mls_context* ctx = new (std::nothrow) mls_context;
+  if (!ctx) return fail(MLS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  ctx->device = device;
+  *out = ctx;
+  return MLS_OK;
+}
+
+void mls_context_destroy(mls_context* ctx) { delete ctx; }
+
+mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
+                   int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                   const mls_grid* grid, int32_t precision, const mls_solve_opts* opts,
+                   float* d_fields, uint8_t* d_degree, void* stream) {
+  g_last_error[0] = '\0';
+  // ---- arguments, checked without touching the device ----
+  if (basis < MLS_BASIS_CONSTANT || basis > MLS_BASIS_QUADRATIC)
+    return fail(MLS_ERR_INVALID_ARG, "basis %d is not an mls_basis", basis);
+  if (n < 1) return fail(MLS_ERR_INVALID_ARG, "n = %lld; need at least one point", (long long)n);
+  if (n > (int64_t)1 << 40) return fail(MLS_ERR_INVALID_ARG, "n = %lld is too large", (long long)n);
+  if (d < 1 || d > max_d_for(basis))
+    return fail(MLS_ERR_INVALID_ARG, "d = %d; basis %d accepts 1..%d attributes", d, basis,
+                max_d_for(basis));
+  if (!weight) return fail(MLS_ERR_INVALID_ARG, "weight is NULL");
+  if (weight->kind < MLS_W_GAUSSIAN || weight->kind > MLS_W_INVPOW)
+    return fail(MLS_ERR_INVALID_ARG, "weight kind %d is not an mls_weight_kind", weight->kind);
+  if (!is_finite(weight->h) || !(weight->h > 0.0))
+    return fail(MLS_ERR_INVALID_ARG, "h = %g; need a finite h > 0", weight->h);
+  if (weight->kind == MLS_W_INVPOW && (!is_finite(weight->alpha) || !(weight->alpha > 0.0)))
+    return fail(MLS_ERR_INVALID_ARG, "alpha = %g; need a finite alpha > 0", weight->alpha);
+  if (!grid) return fail(MLS_ERR_INVALID_ARG, "grid is NULL");
+  if (grid->width < 1 || grid->height < 1)
+    return fail(MLS_ERR_INVALID_ARG, "grid %d x %d; need width, height >= 1", grid->width,
+                grid->height);
+  if ((int64_t)grid->width * grid->height > ((int64_t)1 << 31))
+    return fail(MLS_ERR_INVALID_ARG, "grid %d x %d has more than 2^31 nodes", grid->width,
+                grid->height);
+  if (!is_finite(grid->x0) || !is_finite(grid->y0) || !is_finite(grid->dx) || !is_finite(grid->dy))
+    return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
+  if (precision != MLS_PREC_F64)
+    return fail(MLS_ERR_INVALID_ARG, "precision %d is not an mls_precision", precision);
+  double tau = 1e-8, floor_w = 1e-6;
+  if (opts) {
+    tau = opts->pivot_tol;
+    floor_w = opts->weight_floor;
+    if (!is_finite(tau) || !(tau > 0.0) || !(tau <= 1.0))
+      return fail(MLS_ERR_INVALID_ARG, "pivot_tol = %g; need 0 < tau <= 1", tau);
+    if (!is_finite(floor_w) || floor_w < 0.0)
+      return fail(MLS_ERR_INVALID_ARG, "weight_floor = %g; need a finite value >= 0", floor_w);
+  }
+  if (!d_points) return fail(MLS_ERR_INVALID_ARG, "d_points is NULL");
+  if (!d_values) return fail(MLS_ERR_INVALID_ARG, "d_values is NULL");
+  if (!d_fields) return fail(MLS_ERR_INVALID_ARG, "d_fields is NULL");
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+  if (weight->kind != MLS_W_GAUSSIAN)
+    return fail(MLS_ERR_UNSUPPORTED, "weight kind %d is not available with precision %d",
+                weight->kind, precision);
+
+  // ---- device ----
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  mls_status st;
+  if ((st = check_device_ptr(ctx, d_points, "d_points")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_values, "d_values")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_fields, "d_fields")) != MLS_OK) return st;
+  if (d_degree && (st = check_device_ptr(ctx, d_degree, "d_degree")) != MLS_OK) return st;
+
+  mls::FitArgs a;
+  a.pts = d_points;
+  a.vals = d_values;
+  a.n = n;
+  a.D = d;
+  a.degree = basis;
+  a.wkind = weight->kind;
+  a.h = weight->h;
+  a.alpha = weight->alpha;
+  a.x0 = grid->x0;
+  a.y0 = grid->y0;
+  a.dx = grid->dx;
+  a.dy = grid->dy;
+  a.W = grid->width;
+  a.H = grid->height;
+  a.tau = tau;
+  a.floor_w = floor_w;
+  a.fields = d_fields;
+  a.deg_out = d_degree;
+  e = mls::launch_fit_f64(a, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+  return MLS_OK;
+}
+
+}  // extern "C"

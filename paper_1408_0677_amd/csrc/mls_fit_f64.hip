@@ -1,0 +1,305 @@
+// Float64 matrix-core MLS fit for gfx950 (Muelder et al., Sec. 3.3).
+//
+// Per node p the fit needs the weighted moments of the basis and of
+// basis x attribute products, G_p = sum_i w(p, x_i) g_i with
+//   g_i = [u_x^a u_y^b (a + b <= 2 deg) | b_j(u_i) f_{i,d}]   (F features)
+// in a tile frame u = (x_i - c_T) / h.  Over a tile of nodes this is the
+// product W (nodes x points) . G (points x F): a dense contraction, run here
+// on v_mfma_f64_16x16x4f64 with the point index as the reduction dimension.
+//
+// Workgroup: 256 threads (4 waves) own a tile of 16 columns x 4R rows of
+// nodes.  Each wave owns R row-strips of 16 nodes (one MFMA M-tile each) and
+// all NT = ceil(F / 16) feature N-tiles, so a wave holds R * NT accumulator
+// blocks.  Points stream through LDS in chunks of KT:
+//   1. point coordinates -> LDS (tile-frame u, float64),
+//   2. Gaussian weight factors gx[col][k] = exp(-((x_k - p_col)/h)^2) and
+//      gy[row][k] (the Gaussian separates on a grid, so a tile needs
+//      16 + 4R exponentials per point instead of 64R), and the feature
+//      block G[j][k] in float64,
+//   3. MFMA sweep: the A operand (node x point weight) is gx * gy, built in
+//      registers; B is read from G.  Within each group of 16 points a lane
+//      supplies points k0 + 4 (lane / 16) + j for MFMA j = 0..3, so it reads
+//      four consecutive points with one 32-byte LDS access.
+// After the last chunk the accumulators go through LDS to one node per
+// lane, which runs the float64 degree-ladder solve (mls_solve.h) and stores
+// the D fields and the degree code.  Every node sums its points in the same
+// fixed order, so results are bit-reproducible run to run.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mls_internal.h"
+#include "mls_solve.h"
+
+namespace mls {
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kWaves = 4;
+constexpr int kCols = 16;      // node columns per tile (one M-tile)
+constexpr int KT = 64;         // points per LDS chunk
+constexpr int KS = KT + 4;     // LDS row stride in doubles (keeps 32B alignment)
+
+struct F64Params {
+  const float* pts;
+  const float* vals;
+  int64_t n;
+  int D, F;
+  double h, inv_h;
+  double x0, y0, dx, dy;
+  int W, H, tiles_x;
+  double tau, floor_w;
+  float* fields;
+  uint8_t* deg_out;
+};
+
+template <int DEG, int NT, int R>
+struct F64Layout {
+  static constexpr int kRows = kWaves * R;
+  static constexpr int kFP = NT * 16;                    // padded features
+  // chunk phase
+  static constexpr int kUx = 0;                          // [KT] tile-frame u_x
+  static constexpr int kUy = kUx + KT;                   // [KT]
+  static constexpr int kGx = kUy + KT;                   // [16][KS]
+  static constexpr int kGy = kGx + kCols * KS;           // [kRows][KS]
+  static constexpr int kG = kGy + kRows * KS;            // [kFP][KS]
+  static constexpr int kChunk = kG + kFP * KS;
+  // epilogue phase: per wave [16R nodes][kFP + 1]
+  static constexpr int kEpiStride = kFP + 1;
+  static constexpr int kEpi = kWaves * 16 * R * kEpiStride;
+  static constexpr int kDoubles = kChunk > kEpi ? kChunk : kEpi;
+};
+
+template <int DEG, int NT, int R>
+__global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
+  using L = F64Layout<DEG, NT, R>;
+  constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
+  constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
+  extern __shared__ double lds[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tile_c = blockIdx.x % p.tiles_x;
+  const int tile_r = blockIdx.x / p.tiles_x;
+  const int c0 = tile_c * kCols;
+  const int r0 = tile_r * L::kRows;
+  // tile anchor: the node at the tile's centre (may lie beyond the grid)
+  const double cx = p.x0 + (double)(c0 + kCols / 2) * p.dx;
+  const double cy = p.y0 + (double)(r0 + L::kRows / 2) * p.dy;
+
+  double* ux = lds + L::kUx;
+  double* uy = lds + L::kUy;
+  double* gx = lds + L::kGx;
+  double* gy = lds + L::kGy;
+  double* G = lds + L::kG;
+
+  doublex4 acc[R][NT];
+#pragma unroll
+  for (int t = 0; t < R; ++t)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[t][q] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  const int D = p.D, F = p.F;
+  for (int64_t k0 = 0; k0 < p.n; k0 += KT) {
+    const int kn = (int)((p.n - k0) < KT ? (p.n - k0) : KT);
+    // 1. coordinates in the tile frame
+    if (tid < KT) {
+      double x = 0.0, y = 0.0;
+      if (tid < kn) {
+        x = ((double)p.pts[2 * (k0 + tid)] - cx) * p.inv_h;
+        y = ((double)p.pts[2 * (k0 + tid) + 1] - cy) * p.inv_h;
+      }
+      ux[tid] = x;
+      uy[tid] = y;
+    }
+    __syncthreads();
+    // 2a. separable Gaussian factors; points past n get weight 0
+    for (int e = tid; e < (kCols + L::kRows) * KT; e += kThreads) {
+      const int k = e % KT, row = e / KT;
+      double v = 0.0;
+      if (k < kn) {
+        if (row < kCols) {
+          const double d = ux[k] - (double)(row - kCols / 2) * p.dx * p.inv_h;
+          v = exp(-(d * d));
+          gx[row * KS + k] = v;
+        } else {
+          const int rr = row - kCols;
+          const double d = uy[k] - (double)(rr - L::kRows / 2) * p.dy * p.inv_h;
+          v = exp(-(d * d));
+          gy[rr * KS + k] = v;
+        }
+      } else {
+        if (row < kCols) gx[row * KS + k] = 0.0;
+        else gy[(row - kCols) * KS + k] = 0.0;
+      }
+    }
+    // 2b. moment monomials of the tile-frame coordinates
+    for (int e = tid; e < nmom * KT; e += kThreads) {
+      const int k = e % KT, j = e / KT;
+      // exponents of monomial j (ordered by total degree, then by y power)
+      int t = 0;
+      while ((t + 1) * (t + 2) / 2 <= j) ++t;
+      const int b = j - t * (t + 1) / 2, a = t - b;
+      double v = 1.0;
+      for (int q = 0; q < a; ++q) v *= ux[k];
+      for (int q = 0; q < b; ++q) v *= uy[k];
+      G[j * KS + k] = v;
+    }
+    // 2c. basis x attribute products; consecutive threads read consecutive
+    //     values of one point (coalesced)
+    for (int e = tid; e < KT * D; e += kThreads) {
+      const int k = e / D, d = e % D;
+      const double f = (k < kn) ? (double)p.vals[(k0 + k) * (int64_t)D + d] : 0.0;
+      const double bx = ux[k], by = uy[k];
+      G[(nmom + d) * KS + k] = f;
+      if (m >= 3) {
+        G[(nmom + D + d) * KS + k] = bx * f;
+        G[(nmom + 2 * D + d) * KS + k] = by * f;
+      }
+      if (m >= 6) {
+        G[(nmom + 3 * D + d) * KS + k] = bx * bx * f;
+        G[(nmom + 4 * D + d) * KS + k] = bx * by * f;
+        G[(nmom + 5 * D + d) * KS + k] = by * by * f;
+      }
+    }
+    // padding features stay zero
+    for (int e = tid; e < (L::kFP - F) * KT; e += kThreads) {
+      const int k = e % KT, j = F + e / KT;
+      G[j * KS + k] = 0.0;
+    }
+    __syncthreads();
+
+    // 3. MFMA sweep over the chunk
+    const int i = lane & 15;        // A row (node column) / B column
+    const int kq = (lane >> 4) * 4; // this lane's 4 points in each group of 16
+#pragma unroll 1
+    for (int kg = 0; kg < KT; kg += 16) {
+      const double* gxr = gx + i * KS + kg + kq;
+      double ax[4] = {gxr[0], gxr[1], gxr[2], gxr[3]};
+      double ay[R][4];
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const double* gyr = gy + (wave * R + t) * KS + kg + kq;
+        ay[t][0] = gyr[0]; ay[t][1] = gyr[1]; ay[t][2] = gyr[2]; ay[t][3] = gyr[3];
+      }
+      double bv[NT][4];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const double* gr = G + (q * 16 + i) * KS + kg + kq;
+        bv[q][0] = gr[0]; bv[q][1] = gr[1]; bv[q][2] = gr[2]; bv[q][3] = gr[3];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const double a = ax[j] * ay[t][j];
+#pragma unroll
+          for (int q = 0; q < NT; ++q)
+            acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[q][j], acc[t][q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: accumulators -> LDS [node][feature] -> one node per lane.
+  double* epi = lds + wave * 16 * R * L::kEpiStride;
+#pragma unroll
+  for (int t = 0; t < R; ++t)
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // f64 16x16 MFMA result: lane holds row (lane/16 + 4r), column lane%16
+        const int node = t * 16 + (lane >> 4) + 4 * r;
+        const int feat = q * 16 + (lane & 15);
+        epi[node * L::kEpiStride + feat] = acc[t][q][r];
+      }
+  __syncthreads();
+  const int64_t plane = (int64_t)p.W * p.H;
+  for (int node = lane; node < 16 * R; node += 64) {
+    const int t = node / 16, col = node % 16;
+    const int r = r0 + wave * R + t, c = c0 + col;
+    if (r >= p.H || c >= p.W) continue;
+    // node offset from the anchor, the same expression the weight factors use
+    const double ex = (double)(col - kCols / 2) * p.dx * p.inv_h;
+    const double ey = (double)(wave * R + t - L::kRows / 2) * p.dy * p.inv_h;
+    const int64_t off = (int64_t)r * p.W + c;
+    uint8_t code = solve_node<DEG>(epi + node * L::kEpiStride, D, ex, ey, p.tau,
+                                   p.floor_w, p.fields + off, plane);
+    if (p.deg_out) p.deg_out[off] = code;
+  }
+}
+
+template <int DEG, int NT, int R>
+hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
+  using L = F64Layout<DEG, NT, R>;
+  F64Params p = prm;
+  const int tiles_x = (p.W + kCols - 1) / kCols;
+  const int tiles_y = (p.H + L::kRows - 1) / L::kRows;
+  p.tiles_x = tiles_x;
+  const size_t lds_bytes = sizeof(double) * (size_t)L::kDoubles;
+  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (int64_t)tiles_x * tiles_y;
+  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R>), dim3((unsigned)blocks), dim3(kThreads),
+                     lds_bytes, s, p);
+  return hipGetLastError();
+}
+
+// R (row strips per wave) trades accumulator registers against the number
+// of Gaussian factors per tile.
+template <int DEG, int NT>
+hipError_t launch_nt(const F64Params& p, hipStream_t s) {
+  constexpr int R = NT <= 3 ? 4 : (NT <= 6 ? 2 : 1);
+  return launch_impl<DEG, NT, R>(p, s);
+}
+
+template <int DEG>
+hipError_t launch_deg(const F64Params& p, int nt, hipStream_t s) {
+  switch (nt) {
+    case 1: return launch_nt<DEG, 1>(p, s);
+    case 2: return launch_nt<DEG, 2>(p, s);
+    case 3: return launch_nt<DEG, 3>(p, s);
+    case 4: return launch_nt<DEG, 4>(p, s);
+    case 5: case 6: return launch_nt<DEG, 6>(p, s);
+    case 7: case 8: return launch_nt<DEG, 8>(p, s);
+    case 9: case 10: case 11: case 12: return launch_nt<DEG, 12>(p, s);
+    default: return launch_nt<DEG, 16>(p, s);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
+  const int F = moment_terms(a.degree) + basis_terms(a.degree) * a.D;
+  const int nt = (F + 15) / 16;
+  if (nt > 16) return hipErrorInvalidValue;
+  F64Params p;
+  p.pts = a.pts;
+  p.vals = a.vals;
+  p.n = a.n;
+  p.D = a.D;
+  p.F = F;
+  p.h = a.h;
+  p.inv_h = 1.0 / a.h;
+  p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;
+  p.W = a.W; p.H = a.H;
+  p.tiles_x = 0;
+  p.tau = a.tau;
+  p.floor_w = a.floor_w;
+  p.fields = a.fields;
+  p.deg_out = a.deg_out;
+  switch (a.degree) {
+    case 0: return launch_deg<0>(p, nt, stream);
+    case 1: return launch_deg<1>(p, nt, stream);
+    default: return launch_deg<2>(p, nt, stream);
+  }
+}
+
+}  // namespace mls

@@ -1,0 +1,178 @@
+// Per-node float64 solve of the MLS normal equations (Muelder et al.,
+// Sec. 3.3, Eq. 6-8 generalised to polynomial bases).
+//
+// The contraction kernels accumulate, per node, the weighted moments of the
+// basis in a tile frame: u = (x_i - c_T) / h with c_T the tile anchor, i.e.
+//   g[mono(a, b)]           = sum_i w_i u_x^a u_y^b      (a + b <= 2 deg)
+//   g[nmom + j * D + d]     = sum_i w_i b_j(u_i) f_{i,d}  (j < m)
+// The node's own frame is u_p = u - delta with delta = (p - c_T) / h.  A
+// shift of a complete polynomial space is an invertible linear map T with
+// b(u_p) = T b(u), so the node-frame normal matrix is M_p = T M_t T^T and
+// its right-hand sides R_p = T R_t.  The degree ladder (equilibrated
+// Cholesky, every pivot >= tau, else drop a degree) runs on M_p exactly as
+// the definition states, and the value at the node is
+//   field_d = e_0^T M_p'^{-1} R_p' = y^T R_t,  y = T'^T z,  z = M_p'^{-1} e_0
+// so one factorisation and D dot products of length m give all D fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mls {
+
+// Index of the monomial u_x^a u_y^b in the moment vector (ordered by total
+// degree t = a + b, then by the power of u_y).
+__device__ __forceinline__ constexpr int mono_index(int a, int b) {
+  return (a + b) * (a + b + 1) / 2 + b;
+}
+
+// Exponents (a, b) of the basis terms [1, ux, uy, ux^2, ux uy, uy^2].
+__device__ __forceinline__ constexpr int basis_ax(int j) {
+  return j == 1 ? 1 : (j == 3 ? 2 : (j == 4 ? 1 : 0));
+}
+__device__ __forceinline__ constexpr int basis_ay(int j) {
+  return j == 2 ? 1 : (j == 5 ? 2 : (j == 4 ? 1 : 0));
+}
+
+// Row r of the shift map T (b(u - delta) = T b(u)), entry c.
+__device__ __forceinline__ double shift_entry(int r, int c, double ex, double ey) {
+  switch (r) {
+    case 0: return c == 0 ? 1.0 : 0.0;
+    case 1: return c == 0 ? -ex : (c == 1 ? 1.0 : 0.0);
+    case 2: return c == 0 ? -ey : (c == 2 ? 1.0 : 0.0);
+    case 3: return c == 0 ? ex * ex : (c == 1 ? -2.0 * ex : (c == 3 ? 1.0 : 0.0));
+    case 4: return c == 0 ? ex * ey : (c == 1 ? -ey : (c == 2 ? -ex : (c == 4 ? 1.0 : 0.0)));
+    default: return c == 0 ? ey * ey : (c == 2 ? -2.0 * ey : (c == 5 ? 1.0 : 0.0));
+  }
+}
+
+// Solve one node.  `g` points at the node's F accumulated features
+// (consecutive doubles), `ex, ey` is delta.  Writes field_d to
+// fields[d * plane] (float32) and returns the accepted degree code.
+template <int DEG>
+__device__ uint8_t solve_node(const double* g, int D, double ex, double ey,
+                              double tau, double floor_w, float* fields,
+                              int64_t plane) {
+  constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
+  constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
+  const double sumw = g[0];
+  if (!(sumw >= floor_w)) {
+    for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
+    return 255;
+  }
+  double Mt[m][m];
+#pragma unroll
+  for (int j = 0; j < m; ++j)
+#pragma unroll
+    for (int k = 0; k < m; ++k)
+      Mt[j][k] = g[mono_index(basis_ax(j) + basis_ax(k), basis_ay(j) + basis_ay(k))];
+  double T[m][m];
+#pragma unroll
+  for (int r = 0; r < m; ++r)
+#pragma unroll
+    for (int c = 0; c < m; ++c) T[r][c] = shift_entry(r, c, ex, ey);
+  // Mp = T Mt T^T (lower triangle is all the ladder reads)
+  double TM[m][m];
+#pragma unroll
+  for (int r = 0; r < m; ++r)
+#pragma unroll
+    for (int c = 0; c < m; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= r; ++q) v += T[r][q] * Mt[q][c];
+      TM[r][c] = v;
+    }
+  double Mp[m][m];
+#pragma unroll
+  for (int r = 0; r < m; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= c; ++q) v += TM[r][q] * T[c][q];
+      Mp[r][c] = v;
+    }
+
+  double y[m];
+  int accepted = -1;
+#pragma unroll
+  for (int kd = DEG; kd >= 0; --kd) {
+    const int mk = kd == 0 ? 1 : (kd == 1 ? 3 : 6);
+    double s[m], L[m][m];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      if (j < mk) {
+        ok = ok && (Mp[j][j] > 0.0);
+        s[j] = ok ? 1.0 / sqrt(Mp[j][j]) : 0.0;
+      }
+    }
+    if (!ok) continue;
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      if (j >= mk || !ok) continue;
+      double piv = s[j] * Mp[j][j] * s[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) piv -= L[j][q] * L[j][q];
+      if (!(piv >= tau)) {
+        ok = false;
+        continue;
+      }
+      L[j][j] = sqrt(piv);
+      const double inv = 1.0 / L[j][j];
+#pragma unroll
+      for (int r = j + 1; r < m; ++r) {
+        if (r >= mk) continue;
+        double v = s[r] * Mp[r][j] * s[j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) v -= L[r][q] * L[j][q];
+        L[r][j] = v * inv;
+      }
+    }
+    if (!ok) continue;
+    // z = S A^{-1} S e0:  L q = s0 e0,  L^T w = q,  z = S w
+    double q[m], w[m];
+#pragma unroll
+    for (int r = 0; r < m; ++r) {
+      if (r >= mk) continue;
+      double v = r == 0 ? s[0] : 0.0;
+#pragma unroll
+      for (int c = 0; c < r; ++c) v -= L[r][c] * q[c];
+      q[r] = v / L[r][r];
+    }
+#pragma unroll
+    for (int r = m - 1; r >= 0; --r) {
+      if (r >= mk) continue;
+      double v = q[r];
+#pragma unroll
+      for (int c = r + 1; c < m; ++c)
+        if (c < mk) v -= L[c][r] * w[c];
+      w[r] = v / L[r][r];
+    }
+    // y = T'^T z over the accepted rows
+#pragma unroll
+    for (int c = 0; c < m; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < m; ++r)
+        if (r < mk) v += T[r][c] * (s[r] * w[r]);
+      y[c] = v;
+    }
+    accepted = kd;
+    break;
+  }
+  if (accepted < 0) {  // only when sum w == 0 passes a zero floor
+    for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
+    return 255;
+  }
+  const double* R = g + nmom;
+  for (int d = 0; d < D; ++d) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < m; ++c) v += y[c] * R[c * D + d];
+    fields[(int64_t)d * plane] = (float)v;
+  }
+  return (uint8_t)accepted;
+}
+
+}  // namespace mls

@@ -1,0 +1,41 @@
+"""Comparison of GPU fields against the oracle (test infrastructure).
+
+Error measure: err_d(p) = |f_gpu - f_oracle| / S_d with S_d the range of the
+input values of attribute d.  Nodes are compared where both sides are
+determined and agree on the accepted degree; the "pass set" further requires
+the oracle's smallest equilibrated pivot d_min >= 1e-3.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def compare(gpu_fields, gpu_deg, or_fields, or_deg, or_dmin, values, dmin_pass=1e-3):
+    """Flattened per-node comparison.  gpu_fields/or_fields: (D, P)."""
+    vals = np.asarray(values, dtype=np.float64)
+    S = vals.max(axis=0) - vals.min(axis=0)
+    S = np.where(S > 0, S, 1.0)
+    gf = np.asarray(gpu_fields, dtype=np.float64)
+    of = np.asarray(or_fields, dtype=np.float64)
+    gd = np.asarray(gpu_deg).ravel()
+    od = np.asarray(or_deg).ravel()
+    dm = np.asarray(or_dmin).ravel()
+    both = (gd == od) & (od != 255)
+    passset = both & (dm >= dmin_pass)
+    err = np.abs(gf - of) / S[:, None]
+    out = {
+        "nodes": int(od.size),
+        "degree_mismatch": int(np.sum(gd != od)),
+        "nan_mismatch": int(np.sum((gd == 255) != (od == 255))),
+        "same_degree": int(both.sum()),
+        "pass_set": int(passset.sum()),
+        "max_err_pass": float(err[:, passset].max()) if passset.any() else 0.0,
+        "rms_err_pass": float(np.sqrt(np.mean(err[:, passset] ** 2))) if passset.any() else 0.0,
+        "max_err_same_degree": float(err[:, both].max()) if both.any() else 0.0,
+        "per_field_max_pass": (err[:, passset].max(axis=1).tolist() if passset.any()
+                               else [0.0] * gf.shape[0]),
+    }
+    # NaN exactly where undetermined
+    und = gd == 255
+    out["nan_ok"] = bool(np.all(np.isnan(gf[:, und])) and np.all(np.isfinite(gf[:, ~und])))
+    return out

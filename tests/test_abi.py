@@ -1,0 +1,84 @@
+"""The C ABI library loads, exports every symbol include/mls.h declares, and
+rejects bad arguments before touching the device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mls.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mls_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1408_0677_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1408_0677_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"mls_fit", "mls_context_create", "mls_context_destroy"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1408_0677_amd import _lib
+    assert set(_lib.EXPORTS) == set(names)
+
+
+def test_status_strings(lib):
+    assert lib.mls_status_string(0) == b"MLS_OK"
+    assert lib.mls_status_string(-1) == b"MLS_ERR_INVALID_ARG"
+    assert lib.mls_status_string(-3) == b"MLS_ERR_CAPACITY"
+    assert lib.mls_status_string(12345) == b"MLS_UNKNOWN_STATUS"
+
+
+def _fit(lib, n=10, d=2, basis=1, kind=0, h=0.1, alpha=1.0, grid=(0.0, 0.0, 0.1, 0.1, 8, 8),
+         precision=0, opts=None, pts=1, vals=1, fields=1, ctx=None):
+    from paper_1408_0677_amd import _lib
+    w = _lib.MlsWeight(kind, h, alpha)
+    g = _lib.MlsGrid(*grid)
+    o = None if opts is None else ctypes.byref(_lib.MlsSolveOpts(*opts))
+    fake = ctypes.c_void_p(0x1000)
+    return lib.mls_fit(ctx, fake if pts else None, fake if vals else None, n, d, basis,
+                       ctypes.byref(w), ctypes.byref(g), precision, o,
+                       fake if fields else None, None, None)
+
+
+@pytest.mark.parametrize("kwargs,needle", [
+    (dict(n=0), b"n = 0"),
+    (dict(d=0), b"d = 0"),
+    (dict(d=84), b"d = 84"),
+    (dict(basis=2, d=41), b"d = 41"),
+    (dict(basis=3), b"basis 3"),
+    (dict(kind=7), b"weight kind 7"),
+    (dict(h=0.0), b"h = 0"),
+    (dict(h=float("nan")), b"h = nan"),
+    (dict(h=float("inf")), b"h = inf"),
+    (dict(kind=2, alpha=-1.0), b"alpha"),
+    (dict(grid=(0.0, 0.0, 0.1, 0.1, 0, 8)), b"need width"),
+    (dict(grid=(float("nan"), 0.0, 0.1, 0.1, 8, 8)), b"finite"),
+    (dict(precision=9), b"precision 9"),
+    (dict(opts=(0.0, 1e-6)), b"pivot_tol"),
+    (dict(opts=(1e-8, -1.0)), b"weight_floor"),
+    (dict(pts=0), b"d_points is NULL"),
+    (dict(vals=0), b"d_values is NULL"),
+    (dict(fields=0), b"d_fields is NULL"),
+    (dict(), b"ctx is NULL"),
+])
+def test_invalid_arguments_rejected_before_device(lib, kwargs, needle):
+    st = _fit(lib, **kwargs)
+    assert st == -1, (st, lib.mls_last_error())
+    assert needle in lib.mls_last_error(), lib.mls_last_error()
+
+
+def test_context_create_rejects_null_out(lib):
+    assert lib.mls_context_create(0, None) == -1
