@@ -143,6 +143,39 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
                    const mls_solve_opts* opts, float* d_fields, uint8_t* d_degree,
                    void* stream);
 
+/*
+ * Marching-squares contour lines of fields on a grid (Sec. 3.4, contour
+ * lines of the MLS output; Fig. 5a).
+ *  d_fields   float32 [d][height][width], device (e.g. mls_fit output)
+ *  d          number of fields, >= 1
+ *  grid       node positions as for mls_fit; width, height >= 2
+ *  d_iso      float32 [d][n_iso] isovalues per field, device
+ *  n_iso      isovalues per field, >= 1
+ *  d_cases    uint8 [d][n_iso][height-1][width-1] output, device, or NULL:
+ *             per cell, bit k = (corner k >= iso) with corners
+ *             v0 = f[i][j], v1 = f[i][j+1], v2 = f[i+1][j+1], v3 = f[i+1][j];
+ *             255 where a corner is NaN (no segment)
+ *  d_segments float32 [capacity][4] output (x_from, y_from, x_to, y_to) in
+ *             grid coordinates, device, 16-byte aligned; may be NULL when
+ *             capacity == 0
+ *  d_seg_ids  int32 [capacity][3] output (field, iso index, cell index
+ *             i*(width-1)+j), device, or NULL
+ *  capacity   number of segment slots (>= 0)
+ *  h_count    host output: the number of segments the call produces
+ * Rules: saddle cells (cases 5, 10) join the corners >= iso when the centre
+ * value ((v0+v1)+(v2+v3))/4 >= iso; a crossing is interpolated from the
+ * edge endpoint with the smaller (row, col), so shared edges give identical
+ * points; segments keep the >= iso side on their left; segments are ordered
+ * by (field, iso, cell, segment).  The call waits for the stream to deliver
+ * the count.  If the count exceeds capacity it returns MLS_ERR_CAPACITY
+ * (*h_count still written, d_cases complete, segment contents unspecified);
+ * call again with a larger buffer.
+ */
+mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
+                       const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                       uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
+                       int64_t capacity, int64_t* h_count, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,11 +9,13 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmls_hip.so")
+# MLS_HIP_LIB may name another build of the same sources (used to compare
+# kernel variants); by default the in-tree library is loaded.
+LIB_PATH = os.environ.get("MLS_HIP_LIB") or os.path.join(HERE, "libmls_hip.so")
 
 # Symbols declared in include/mls.h.
 EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
-           "mls_context_destroy", "mls_fit")
+           "mls_context_destroy", "mls_fit", "mls_contour")
 
 
 class MlsGrid(ctypes.Structure):
@@ -57,5 +59,8 @@ def load():
                             ctypes.POINTER(MlsGrid), i32,
                             ctypes.POINTER(MlsSolveOpts), P, P, P]
     lib.mls_fit.restype = ctypes.c_int
+    lib.mls_contour.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P, i64,
+                                ctypes.POINTER(i64), P]
+    lib.mls_contour.restype = ctypes.c_int
     _lib = lib
     return lib

@@ -116,3 +116,46 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
                              _stream_handle(stream))
     _check(st, "mls_fit")
     return out, degree_out
+
+
+CAPACITY_ERROR = -3
+
+
+def contour(fields, grid: dict, iso, want_cases: bool = True, want_ids: bool = True,
+            capacity: int | None = None, ctx: Context | None = None, stream=None):
+    """Marching-squares segments of ``fields`` (D, H, W) at isovalues ``iso``
+    (D, n_iso), both float32 device tensors.
+
+    Returns ``(segments (S, 4), ids (S, 3) or None, cases (D, n_iso, H-1,
+    W-1) or None)``.  Without ``capacity`` the call first asks for the count
+    and then runs again with an exact buffer.
+    """
+    import torch
+    assert fields.dtype == torch.float32 and fields.is_contiguous()
+    if fields.dim() == 2:
+        fields = fields.unsqueeze(0)
+    D, H, W = fields.shape
+    iso = iso.to(device=fields.device, dtype=torch.float32).reshape(D, -1).contiguous()
+    n_iso = iso.shape[1]
+    dev = fields.device
+    ctx = ctx or default_context(dev.index)
+    g = grid_struct(grid)
+    cases = (torch.empty((D, n_iso, H - 1, W - 1), dtype=torch.uint8, device=dev)
+             if want_cases else None)
+    lib = _lib.load()
+    count = ctypes.c_int64(0)
+    cap = 0 if capacity is None else int(capacity)
+    while True:
+        segs = torch.empty((max(cap, 1), 4), dtype=torch.float32, device=dev)
+        ids = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=dev) if want_ids else None
+        st = lib.mls_contour(ctx.handle, _ptr(fields), D, ctypes.byref(g), _ptr(iso), n_iso,
+                             _ptr(cases), _ptr(segs) if cap > 0 else None,
+                             _ptr(ids) if cap > 0 else None, cap, ctypes.byref(count),
+                             _stream_handle(stream))
+        if st == CAPACITY_ERROR and (capacity is None or cap == 0):
+            cap = int(count.value)
+            continue
+        _check(st, "mls_contour")
+        break
+    n = int(count.value)
+    return segs[:n], (ids[:n] if ids is not None else None), cases

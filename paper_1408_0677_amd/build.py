@@ -33,31 +33,36 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, obj: str) -> str:
-    cmd = [_hipcc(), *COMMON, "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
+def _compile(src: str, obj: str, defines=()) -> str:
+    cmd = [_hipcc(), *COMMON, *[f"-D{d}" for d in defines],
+           "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, out: str | None = None, defines=(), srcdir: str | None = None) -> str:
+    """Compile and link; ``out``, ``defines`` (extra -D flags) and ``srcdir``
+    serve variant builds outside the tree."""
+    src_root = srcdir or CSRC
+    srcs = sorted(glob.glob(os.path.join(src_root, "*.hip")) + glob.glob(os.path.join(src_root, "*.cpp")))
+    lib = out or LIB
+    objdir = os.path.join(os.path.dirname(lib), "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
     workers = min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(workers) as ex:
-        for o in ex.map(_compile, srcs, objs):
+        for o in ex.map(lambda s_o: _compile(*s_o, defines), zip(srcs, objs)):
             if verbose:
                 print("compiled", os.path.basename(o))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -14,6 +14,11 @@
 
 struct mls_context {
   int device;
+  // device scratch, grown on demand (contour counts, offsets, tile sums)
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  // pinned host word for counts read back by mls_contour
+  int64_t* pinned = nullptr;
 };
 
 namespace {
@@ -58,6 +63,28 @@ mls_status check_device_ptr(const mls_context* ctx, const void* ptr, const char*
   return MLS_OK;
 }
 
+// Make sure ctx->scratch holds at least `bytes`.
+mls_status ensure_scratch(mls_context* ctx, size_t bytes) {
+  if (ctx->scratch_bytes >= bytes) return MLS_OK;
+  if (ctx->scratch) {
+    hipError_t e = hipFree(ctx->scratch);  // synchronises with queued work
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    if (e != hipSuccess) return device_fail(e, "hipFree");
+  }
+  size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+  hipError_t e = hipMalloc(&ctx->scratch, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->scratch = nullptr;
+    return fail(MLS_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes failed", want);
+  }
+  ctx->scratch_bytes = want;
+  return MLS_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
 }  // namespace
 
 extern "C" {
@@ -98,7 +125,14 @@ mls_status mls_context_create(int32_t device, mls_context** out) {
   return MLS_OK;
 }
 
-void mls_context_destroy(mls_context* ctx) { delete ctx; }
+void mls_context_destroy(mls_context* ctx) {
+  if (!ctx) return;
+  if (hipSetDevice(ctx->device) == hipSuccess) {
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  }
+  delete ctx;
+}
 
 mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
                    int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
@@ -178,6 +212,93 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   a.deg_out = d_degree;
   e = mls::launch_fit_f64(a, (hipStream_t)stream);
   if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+  return MLS_OK;
+}
+
+mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
+                       const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                       uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
+                       int64_t capacity, int64_t* h_count, void* stream) {
+  g_last_error[0] = '\0';
+  if (d < 1) return fail(MLS_ERR_INVALID_ARG, "d = %d; need at least one field", d);
+  if (!grid) return fail(MLS_ERR_INVALID_ARG, "grid is NULL");
+  if (grid->width < 2 || grid->height < 2)
+    return fail(MLS_ERR_INVALID_ARG, "grid %d x %d; contours need width, height >= 2",
+                grid->width, grid->height);
+  if (!is_finite(grid->x0) || !is_finite(grid->y0) || !is_finite(grid->dx) || !is_finite(grid->dy))
+    return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
+  if (n_iso < 1) return fail(MLS_ERR_INVALID_ARG, "n_iso = %d; need at least one", n_iso);
+  if (capacity < 0) return fail(MLS_ERR_INVALID_ARG, "capacity = %lld", (long long)capacity);
+  if (!h_count) return fail(MLS_ERR_INVALID_ARG, "h_count is NULL");
+  if (!d_fields) return fail(MLS_ERR_INVALID_ARG, "d_fields is NULL");
+  if (!d_iso) return fail(MLS_ERR_INVALID_ARG, "d_iso is NULL");
+  if (capacity > 0 && !d_segments)
+    return fail(MLS_ERR_INVALID_ARG, "d_segments is NULL with capacity %lld", (long long)capacity);
+  if (d_segments && ((uintptr_t)d_segments % 16) != 0)
+    return fail(MLS_ERR_INVALID_ARG, "d_segments must be 16-byte aligned");
+  const int64_t cells = (int64_t)(grid->width - 1) * (grid->height - 1);
+  const int64_t blocks = (int64_t)d * ((cells + 255) / 256);
+  if (blocks * 256 >= ((int64_t)1 << 32) || cells >= ((int64_t)1 << 31))
+    return fail(MLS_ERR_INVALID_ARG, "%d fields of %d x %d nodes exceed one launch", d,
+                grid->width, grid->height);
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  mls_status st;
+  if ((st = check_device_ptr(ctx, d_fields, "d_fields")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_iso, "d_iso")) != MLS_OK) return st;
+  if (d_cases && (st = check_device_ptr(ctx, d_cases, "d_cases")) != MLS_OK) return st;
+  if (d_segments && (st = check_device_ptr(ctx, d_segments, "d_segments")) != MLS_OK) return st;
+  if (d_seg_ids && (st = check_device_ptr(ctx, d_seg_ids, "d_seg_ids")) != MLS_OK) return st;
+
+  const int64_t entries = mls::contour_scratch_entries(d, n_iso, grid->width, grid->height);
+  const int64_t tiles = mls::contour_scan_tiles(entries);
+  const size_t off_counts = 0;
+  const size_t off_offsets = align_up(sizeof(int32_t) * (size_t)entries, 256);
+  const size_t off_tiles = off_offsets + align_up(sizeof(int64_t) * (size_t)entries, 256);
+  const size_t off_total = off_tiles + align_up(sizeof(int64_t) * (size_t)tiles, 256);
+  const size_t need = off_total + 256;
+  if ((st = ensure_scratch(ctx, need)) != MLS_OK) return st;
+  if (!ctx->pinned) {
+    e = hipHostMalloc((void**)&ctx->pinned, sizeof(int64_t) * 4, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ctx->pinned = nullptr;
+      (void)hipGetLastError();
+      return fail(MLS_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+    }
+  }
+  char* base = (char*)ctx->scratch;
+  mls::ContourArgs a;
+  a.fields = d_fields;
+  a.iso = d_iso;
+  a.D = d;
+  a.n_iso = n_iso;
+  a.W = grid->width;
+  a.H = grid->height;
+  a.x0 = grid->x0;
+  a.y0 = grid->y0;
+  a.dx = grid->dx;
+  a.dy = grid->dy;
+  a.cases = d_cases;
+  a.segs = d_segments;
+  a.ids = d_seg_ids;
+  a.capacity = capacity;
+  a.counts = (int32_t*)(base + off_counts);
+  a.offsets = (int64_t*)(base + off_offsets);
+  a.tile_sums = (int64_t*)(base + off_tiles);
+  a.total = (int64_t*)(base + off_total);
+  hipStream_t s = (hipStream_t)stream;
+  e = mls::launch_contour(a, s);
+  if (e != hipSuccess) return device_fail(e, "contour kernel launch");
+  e = hipMemcpyAsync(ctx->pinned, a.total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return device_fail(e, "count read-back");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_fail(e, "stream synchronise");
+  *h_count = ctx->pinned[0];
+  if (*h_count > capacity)
+    return fail(MLS_ERR_CAPACITY, "%lld segments, capacity %lld", (long long)*h_count,
+                (long long)capacity);
   return MLS_OK;
 }
 

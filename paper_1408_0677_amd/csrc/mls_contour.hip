@@ -1,0 +1,326 @@
+// Marching-squares contour lines of MLS fields (Muelder et al., Sec. 3.4:
+// contour lines are the simplest rendering of the MLS output; the
+// extraction rule below is this library's choice).
+//
+// Cell (i, j) of an H x W field has corners v0 = f[i][j], v1 = f[i][j+1],
+// v2 = f[i+1][j+1], v3 = f[i+1][j]; bit k of its case is (v_k >= iso).  A NaN
+// corner (undetermined node) gives case 255 and no segment.  Saddles 5 and 10
+// join the above corners when the centre ((v0 + v1) + (v2 + v3)) / 4 >= iso.
+// A crossing on an edge is interpolated from the edge endpoint with the
+// smaller (row, col), so the two cells sharing an edge produce the same bits.
+// Segments run with the >= iso side on their left.  Edge numbering:
+// 0 bottom (v0-v1), 1 right (v1-v2), 2 top (v3-v2), 3 left (v0-v3).
+//
+// Three passes keep the output in (field, iso, cell, segment) order without
+// atomics, so it is deterministic:
+//   count:  one thread per cell, all isovalues of one field per block
+//           (the four corners are loaded once), per-block segment counts;
+//   scan:   exclusive scan of the counts in (field, iso, block) order;
+//   emit:   recompute, block-local prefix sum, write segments and ids.
+// The work is bound by reading the fields once per pass (HBM).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mls_internal.h"
+
+namespace mls {
+namespace {
+
+constexpr int kCellsPerBlock = 256;
+constexpr int kScanTile = 1024;      // entries per block of the first scan level
+
+// Segments per case: from-edge, to-edge pairs; cases 5 and 10 are resolved
+// by the saddle rule in case_segments().
+__constant__ signed char kOneSegment[16][2] = {
+    {-1, -1}, {0, 3}, {1, 0}, {1, 3}, {2, 1}, {-1, -1}, {2, 0}, {2, 3},
+    {3, 2},   {0, 2}, {-1, -1}, {1, 2}, {3, 1}, {0, 1}, {3, 0}, {-1, -1}};
+
+struct Corners {
+  float v0, v1, v2, v3;
+  bool valid;
+};
+
+__device__ __forceinline__ Corners load_corners(const float* f, int W, int i, int j) {
+  Corners c;
+  c.v0 = f[(int64_t)i * W + j];
+  c.v1 = f[(int64_t)i * W + j + 1];
+  c.v2 = f[(int64_t)(i + 1) * W + j + 1];
+  c.v3 = f[(int64_t)(i + 1) * W + j];
+  c.valid = !(isnan(c.v0) || isnan(c.v1) || isnan(c.v2) || isnan(c.v3));
+  return c;
+}
+
+__device__ __forceinline__ int cell_case(const Corners& c, float iso) {
+  if (!c.valid) return 255;
+  return (c.v0 >= iso ? 1 : 0) | (c.v1 >= iso ? 2 : 0) | (c.v2 >= iso ? 4 : 0) |
+         (c.v3 >= iso ? 8 : 0);
+}
+
+// Fills seg[][2] with (from, to) edges; returns the segment count.
+__device__ __forceinline__ int case_segments(int cs, const Corners& c, float iso, int seg[2][2]) {
+#pragma clang fp contract(off)
+  if (cs == 5 || cs == 10) {
+    const float centre = ((c.v0 + c.v1) + (c.v2 + c.v3)) * 0.25f;
+    const bool joined = centre >= iso;
+    if (cs == 5) {
+      seg[0][0] = 0; seg[0][1] = joined ? 1 : 3;
+      seg[1][0] = 2; seg[1][1] = joined ? 3 : 1;
+    } else {
+      seg[0][0] = joined ? 3 : 1; seg[0][1] = 0;
+      seg[1][0] = joined ? 1 : 3; seg[1][1] = 2;
+    }
+    return 2;
+  }
+  if (cs == 255 || kOneSegment[cs][0] < 0) return 0;
+  seg[0][0] = kOneSegment[cs][0];
+  seg[0][1] = kOneSegment[cs][1];
+  return 1;
+}
+
+__device__ __forceinline__ int segment_count(int cs) {
+  return (cs == 5 || cs == 10) ? 2 : ((cs == 0 || cs == 15 || cs == 255) ? 0 : 1);
+}
+
+struct GridD {
+  double x0, y0, dx, dy;
+};
+
+// World position of the crossing on edge e of cell (i, j).
+__device__ __forceinline__ void edge_point(int e, const Corners& c, float iso, int i, int j,
+                                           const GridD& g, float* x, float* y) {
+#pragma clang fp contract(off)
+  float va, vb;
+  switch (e) {
+    case 0: va = c.v0; vb = c.v1; break;
+    case 1: va = c.v1; vb = c.v2; break;
+    case 2: va = c.v3; vb = c.v2; break;
+    default: va = c.v0; vb = c.v3; break;
+  }
+  const float t = (iso - va) / (vb - va);
+  double px, py;
+  switch (e) {
+    case 0: px = g.x0 + ((double)j + (double)t) * g.dx; py = g.y0 + (double)i * g.dy; break;
+    case 1: px = g.x0 + (double)(j + 1) * g.dx; py = g.y0 + ((double)i + (double)t) * g.dy; break;
+    case 2: px = g.x0 + ((double)j + (double)t) * g.dx; py = g.y0 + (double)(i + 1) * g.dy; break;
+    default: px = g.x0 + (double)j * g.dx; py = g.y0 + ((double)i + (double)t) * g.dy; break;
+  }
+  *x = (float)px;
+  *y = (float)py;
+}
+
+// Block-wide exclusive sum of one int per thread (256 threads).
+__device__ __forceinline__ int block_exclusive_sum(int v, int* total, int* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int n = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += n;
+  }
+  if (lane == 63) scratch[wave] = incl;
+  __syncthreads();
+  int base = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < kCellsPerBlock / 64; ++w) {
+    const int s = scratch[w];
+    if (w < wave) base += s;
+    sum += s;
+  }
+  __syncthreads();
+  *total = sum;
+  return base + incl - v;
+}
+
+struct ContourParams {
+  const float* fields;
+  const float* iso;      // [D][n_iso]
+  int D, n_iso, W, H;
+  int64_t cells;         // (H - 1) * (W - 1)
+  int64_t nchunk;        // blocks per field
+  uint8_t* cases;        // [D][n_iso][cells] or null
+  int32_t* counts;       // [D][n_iso][nchunk]
+  int64_t* offsets;      // [D][n_iso][nchunk], exclusive within scan tiles
+  const int64_t* tile_prefix;  // exclusive prefix of scan tiles
+  float* segs;           // [cap][4]
+  int32_t* ids;          // [cap][3] or null
+  int64_t capacity;
+  GridD g;
+};
+
+__global__ __launch_bounds__(kCellsPerBlock) void contour_count_kernel(ContourParams p) {
+  __shared__ int scratch[kCellsPerBlock / 64];
+  const int d = blockIdx.x / p.nchunk;
+  const int64_t chunk = blockIdx.x % p.nchunk;
+  const int64_t cell = chunk * kCellsPerBlock + threadIdx.x;
+  const bool in = cell < p.cells;
+  const int cw = p.W - 1;
+  Corners c = {0.f, 0.f, 0.f, 0.f, false};
+  int i = 0, j = 0;
+  const float* f = p.fields + (int64_t)d * p.W * p.H;
+  if (in) {
+    i = (int)(cell / cw);
+    j = (int)(cell % cw);
+    c = load_corners(f, p.W, i, j);
+  }
+  for (int k = 0; k < p.n_iso; ++k) {
+    const float iso = p.iso[d * p.n_iso + k];
+    const int cs = in ? cell_case(c, iso) : 255;
+    if (in && p.cases) p.cases[((int64_t)d * p.n_iso + k) * p.cells + cell] = (uint8_t)cs;
+    int total;
+    block_exclusive_sum(in ? segment_count(cs) : 0, &total, scratch);
+    if (threadIdx.x == 0) p.counts[((int64_t)d * p.n_iso + k) * p.nchunk + chunk] = total;
+  }
+}
+
+// First scan level: exclusive scan inside tiles of kScanTile entries.
+__global__ __launch_bounds__(256) void scan_tiles_kernel(const int32_t* in, int64_t* out,
+                                                         int64_t* tile_sums, int64_t n) {
+  __shared__ int64_t wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int64_t v[4];
+  int64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t idx = base + 4 * t + q;
+    v[q] = idx < n ? (int64_t)in[idx] : 0;
+    s += v[q];
+  }
+  int64_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t nb = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += nb;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int64_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) wbase += wsum[w];
+    tot += wsum[w];
+  }
+  int64_t run = wbase + incl - s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t idx = base + 4 * t + q;
+    if (idx < n) out[idx] = run;
+    run += v[q];
+  }
+  if (t == 0) tile_sums[blockIdx.x] = tot;
+}
+
+// Second level: one block scans the tile sums in place and writes the total.
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t* sums, int64_t ntiles,
+                                                         int64_t* total) {
+  __shared__ int64_t wsum[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t per = (ntiles + 1023) / 1024;
+  const int64_t lo = t * per, hi = lo + per < ntiles ? lo + per : ntiles;
+  int64_t s = 0;
+  for (int64_t q = lo; q < hi; ++q) s += sums[q];
+  int64_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t nb = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += nb;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int64_t wbase = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) wbase += wsum[w];
+    tot += wsum[w];
+  }
+  int64_t run = wbase + incl - s;
+  for (int64_t q = lo; q < hi; ++q) {
+    const int64_t v = sums[q];
+    sums[q] = run;
+    run += v;
+  }
+  if (t == 0) *total = tot;
+}
+
+__global__ __launch_bounds__(kCellsPerBlock) void contour_emit_kernel(ContourParams p) {
+  __shared__ int scratch[kCellsPerBlock / 64];
+  const int d = blockIdx.x / p.nchunk;
+  const int64_t chunk = blockIdx.x % p.nchunk;
+  const int64_t cell = chunk * kCellsPerBlock + threadIdx.x;
+  const bool in = cell < p.cells;
+  const int cw = p.W - 1;
+  Corners c = {0.f, 0.f, 0.f, 0.f, false};
+  int i = 0, j = 0;
+  const float* f = p.fields + (int64_t)d * p.W * p.H;
+  if (in) {
+    i = (int)(cell / cw);
+    j = (int)(cell % cw);
+    c = load_corners(f, p.W, i, j);
+  }
+  for (int k = 0; k < p.n_iso; ++k) {
+    const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
+    const float iso = p.iso[d * p.n_iso + k];
+    const int cs = in ? cell_case(c, iso) : 255;
+    int seg[2][2];
+    const int ns = in ? case_segments(cs, c, iso, seg) : 0;
+    int total;
+    const int local = block_exclusive_sum(ns, &total, scratch);
+    if (total == 0) continue;
+    const int64_t base = p.offsets[slot] + p.tile_prefix[slot / kScanTile] + local;
+    for (int q = 0; q < ns; ++q) {
+      const int64_t o = base + q;
+      if (o >= p.capacity) break;
+      float x0, y0, x1, y1;
+      edge_point(seg[q][0], c, iso, i, j, p.g, &x0, &y0);
+      edge_point(seg[q][1], c, iso, i, j, p.g, &x1, &y1);
+      reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
+      if (p.ids) {
+        p.ids[3 * o] = d;
+        p.ids[3 * o + 1] = k;
+        p.ids[3 * o + 2] = (int32_t)cell;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int64_t contour_scratch_entries(int32_t D, int32_t n_iso, int32_t W, int32_t H) {
+  const int64_t cells = (int64_t)(W - 1) * (H - 1);
+  const int64_t nchunk = (cells + kCellsPerBlock - 1) / kCellsPerBlock;
+  return (int64_t)D * n_iso * nchunk;
+}
+
+int64_t contour_scan_tiles(int64_t entries) { return (entries + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_contour(const ContourArgs& a, hipStream_t s) {
+  ContourParams p;
+  p.fields = a.fields;
+  p.iso = a.iso;
+  p.D = a.D;
+  p.n_iso = a.n_iso;
+  p.W = a.W;
+  p.H = a.H;
+  p.cells = (int64_t)(a.W - 1) * (a.H - 1);
+  p.nchunk = (p.cells + kCellsPerBlock - 1) / kCellsPerBlock;
+  p.cases = a.cases;
+  p.counts = a.counts;
+  p.offsets = a.offsets;
+  p.tile_prefix = a.tile_sums;
+  p.segs = a.segs;
+  p.ids = a.ids;
+  p.capacity = a.capacity;
+  p.g = GridD{a.x0, a.y0, a.dx, a.dy};
+  const int64_t blocks = (int64_t)a.D * p.nchunk;
+  const int64_t entries = blocks * a.n_iso;
+  const int64_t tiles = contour_scan_tiles(entries);
+  hipLaunchKernelGGL(contour_count_kernel, dim3((unsigned)blocks), dim3(kCellsPerBlock), 0, s, p);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, a.counts,
+                     a.offsets, a.tile_sums, entries);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, a.tile_sums, tiles, a.total);
+  if (a.capacity > 0)
+    hipLaunchKernelGGL(contour_emit_kernel, dim3((unsigned)blocks), dim3(kCellsPerBlock), 0, s,
+                       p);
+  return hipGetLastError();
+}
+
+}  // namespace mls

@@ -36,11 +36,22 @@ namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+#ifndef MLS_F64_KT
+#define MLS_F64_KT 64
+#endif
+#ifndef MLS_F64_EPI_WAVES
+#define MLS_F64_EPI_WAVES 2
+#endif
+
 constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 constexpr int kCols = 16;      // node columns per tile (one M-tile)
-constexpr int KT = 64;         // points per LDS chunk
+constexpr int KT = MLS_F64_KT; // points per LDS chunk
 constexpr int KS = KT + 4;     // LDS row stride in doubles (keeps 32B alignment)
+// Waves that run the epilogue at the same time: the epilogue needs a
+// [nodes][features] float64 staging area per wave, and sharing it keeps the
+// kernel's LDS small enough for two workgroups per CU.
+constexpr int kEpiWaves = MLS_F64_EPI_WAVES;
 
 struct F64Params {
   const float* pts;
@@ -66,11 +77,15 @@ struct F64Layout {
   static constexpr int kGy = kGx + kCols * KS;           // [kRows][KS]
   static constexpr int kG = kGy + kRows * KS;            // [kFP][KS]
   static constexpr int kChunk = kG + kFP * KS;
-  // epilogue phase: per wave [16R nodes][kFP + 1]
+  // epilogue phase: per solving wave [16R nodes][kFP + 1]
   static constexpr int kEpiStride = kFP + 1;
-  static constexpr int kEpi = kWaves * 16 * R * kEpiStride;
+  static constexpr int kEpi = kEpiWaves * 16 * R * kEpiStride;
   static constexpr int kDoubles = kChunk > kEpi ? kChunk : kEpi;
 };
+
+template <int DEG, int R>
+__device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
+                                 int wave, int r0, int c0, int rows, int64_t plane);
 
 template <int DEG, int NT, int R>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
@@ -205,31 +220,47 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     __syncthreads();
   }
 
-  // Epilogue: accumulators -> LDS [node][feature] -> one node per lane.
-  double* epi = lds + wave * 16 * R * L::kEpiStride;
-#pragma unroll
-  for (int t = 0; t < R; ++t)
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // f64 16x16 MFMA result: lane holds row (lane/16 + 4r), column lane%16
-        const int node = t * 16 + (lane >> 4) + 4 * r;
-        const int feat = q * 16 + (lane & 15);
-        epi[node * L::kEpiStride + feat] = acc[t][q][r];
-      }
-  __syncthreads();
+  // Epilogue: accumulators -> LDS [node][feature] -> one node per lane,
+  // kEpiWaves waves at a time.  (The main loop ended with a barrier.)
   const int64_t plane = (int64_t)p.W * p.H;
+#pragma unroll 1
+  for (int g = 0; g < kWaves; g += kEpiWaves) {
+    const bool mine = wave >= g && wave < g + kEpiWaves;
+    double* epi = lds + (wave - g) * 16 * R * L::kEpiStride;
+    if (mine) {
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            // f64 16x16 MFMA result: lane holds row (lane/16 + 4r), column lane%16
+            const int node = t * 16 + (lane >> 4) + 4 * r;
+            const int feat = q * 16 + (lane & 15);
+            epi[node * L::kEpiStride + feat] = acc[t][q][r];
+          }
+    }
+    __syncthreads();
+    if (mine) solve_tile_nodes<DEG, R>(p, epi, L::kEpiStride, lane, wave, r0, c0, L::kRows, plane);
+    __syncthreads();
+  }
+}
+
+// One node per lane: the float64 ladder solve of the nodes of one wave.
+template <int DEG, int R>
+__device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
+                                 int wave, int r0, int c0, int rows, int64_t plane) {
+  const int D = p.D;
   for (int node = lane; node < 16 * R; node += 64) {
     const int t = node / 16, col = node % 16;
     const int r = r0 + wave * R + t, c = c0 + col;
     if (r >= p.H || c >= p.W) continue;
     // node offset from the anchor, the same expression the weight factors use
     const double ex = (double)(col - kCols / 2) * p.dx * p.inv_h;
-    const double ey = (double)(wave * R + t - L::kRows / 2) * p.dy * p.inv_h;
+    const double ey = (double)(wave * R + t - rows / 2) * p.dy * p.inv_h;
     const int64_t off = (int64_t)r * p.W + c;
-    uint8_t code = solve_node<DEG>(epi + node * L::kEpiStride, D, ex, ey, p.tau,
-                                   p.floor_w, p.fields + off, plane);
+    uint8_t code = solve_node<DEG>(epi + node * stride, D, ex, ey, p.tau, p.floor_w,
+                                   p.fields + off, plane);
     if (p.deg_out) p.deg_out[off] = code;
   }
 }

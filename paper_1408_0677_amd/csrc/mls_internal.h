@@ -30,4 +30,25 @@ __host__ __device__ constexpr int moment_terms(int deg) { return deg == 0 ? 1 : 
 // Float64 matrix-core fit (Gaussian weight).  Returns a hipError_t.
 hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream);
 
+// Marching squares over D fields at n_iso isovalues each.
+struct ContourArgs {
+  const float* fields;   // [D][H][W]
+  const float* iso;      // [D][n_iso]
+  int32_t D, n_iso, W, H;
+  double x0, y0, dx, dy;
+  uint8_t* cases;        // [D][n_iso][(H-1)(W-1)] or null
+  float* segs;           // [capacity][4]
+  int32_t* ids;          // [capacity][3] or null
+  int64_t capacity;
+  // scratch (library-owned): contour_scratch_entries() int32 counts and
+  // int64 offsets, contour_scan_tiles() int64 tile sums, one int64 total
+  int32_t* counts;
+  int64_t* offsets;
+  int64_t* tile_sums;
+  int64_t* total;
+};
+int64_t contour_scratch_entries(int32_t D, int32_t n_iso, int32_t W, int32_t H);
+int64_t contour_scan_tiles(int64_t entries);
+hipError_t launch_contour(const ContourArgs& a, hipStream_t stream);
+
 }  // namespace mls

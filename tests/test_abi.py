@@ -82,3 +82,37 @@ def test_invalid_arguments_rejected_before_device(lib, kwargs, needle):
 
 def test_context_create_rejects_null_out(lib):
     assert lib.mls_context_create(0, None) == -1
+
+
+def _contour(lib, d=1, grid=(0.0, 0.0, 0.1, 0.1, 8, 8), n_iso=2, capacity=10, fields=1,
+             iso=1, segs=1, count=True, ctx=None, seg_addr=0x1000):
+    from paper_1408_0677_amd import _lib
+    g = _lib.MlsGrid(*grid)
+    fake = ctypes.c_void_p(0x1000)
+    cnt = ctypes.c_int64(-7)
+    st = lib.mls_contour(ctx, fake if fields else None, d, ctypes.byref(g),
+                         fake if iso else None, n_iso, None,
+                         ctypes.c_void_p(seg_addr) if segs else None, None, capacity,
+                         ctypes.byref(cnt) if count else None, None)
+    return st, cnt.value
+
+
+@pytest.mark.parametrize("kwargs,needle", [
+    (dict(d=0), b"d = 0"),
+    (dict(grid=(0.0, 0.0, 0.1, 0.1, 1, 8)), b"width, height >= 2"),
+    (dict(grid=(0.0, float("inf"), 0.1, 0.1, 8, 8)), b"finite"),
+    (dict(n_iso=0), b"n_iso = 0"),
+    (dict(capacity=-1), b"capacity"),
+    (dict(count=False), b"h_count is NULL"),
+    (dict(fields=0), b"d_fields is NULL"),
+    (dict(iso=0), b"d_iso is NULL"),
+    (dict(segs=0), b"d_segments is NULL"),
+    (dict(seg_addr=0x1004), b"16-byte aligned"),
+    (dict(d=100000, grid=(0.0, 0.0, 1.0, 1.0, 1000, 1000)), b"exceed one launch"),
+    (dict(), b"ctx is NULL"),
+])
+def test_contour_invalid_arguments(lib, kwargs, needle):
+    st, cnt = _contour(lib, **kwargs)
+    assert st == -1, (st, lib.mls_last_error())
+    assert needle in lib.mls_last_error(), lib.mls_last_error()
+    assert cnt == -7          # nothing written on rejection
