@@ -2,11 +2,16 @@
 
 One step = one pass of the whole path over the 1024^2-node workload:
 N = 5,000 points drawn from an 8-component Gaussian mixture, D = 13 smooth
-attributes, linear basis, Gaussian weight h = 0.03 (mls_fit: weights,
-float64 contraction, float64 per-node solve), with the inputs resident in
-HBM.  Prints one JSON line with throughput (node x point pairs per second),
-fields per second, p50/p99 step latency, the fit kernel's roofline figures,
-and the FP64 CPU oracle timed on a sample of the same workload.
+attributes, linear basis, Gaussian weight h = 0.03.  mls_fit (weights,
+float64 contraction, float64 per-node solve) followed by mls_contour (10
+isovalues per field, marching squares), inputs resident in HBM.  Prints one
+JSON line with throughput (node x point pairs per second), fields per
+second, p50/p99 step latency, the fit kernel's roofline figures, and the FP64
+CPU oracle timed on a sample of the same workload.
+
+--copy-calibration additionally runs a plain 256 MiB device copy after the
+timed region, so that a counter run (FETCH_SIZE / WRITE_SIZE) of this script
+sees a kernel of known traffic next to the fit kernel.
 """
 from __future__ import annotations
 
@@ -51,12 +56,86 @@ def cpu_baseline(w, row_stride=16):
                       f"{w.n} points), FP64, {dt:.2f} s"}
 
 
+def serve_bench(args):
+    """The served form on the request mix: closed-loop saturation for the
+    16-bit served precision and the plain path, then Poisson arrivals at
+    0.5, 0.8 and 1.0 times the saturation rate."""
+    import torch
+    from paper_1408_0677_amd import api, workloads as wl
+
+    reqs = wl.c4_requests(count=args.requests)
+    dev = torch.device("cuda:0")
+    budget = 2 << 30
+    slot_scratch = max(api.fit_scratch_bytes(r.n, r.d, r.grid, "fp16") for r in reqs) + (1 << 20)
+    srv = api.Server(0, budget + args.slots * slot_scratch, args.slots, slot_scratch)
+    pids = [srv.put_points(torch.from_numpy(r.points).to(dev),
+                           torch.from_numpy(r.values).to(dev)) for r in reqs]
+    pairs = [r.grid["width"] * r.grid["height"] * r.n for r in reqs]
+
+    def run(prec, arrivals=None):
+        """Submit every request (at its arrival time if given), collect
+        results; returns (wall seconds, latencies)."""
+        outs = {}
+        pending = {}
+        lat = []
+        t0 = time.perf_counter()
+        k = 0
+        while k < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while k < len(reqs) and (arrivals is None or arrivals[k] <= now):
+                r = reqs[k]
+                out = torch.empty((r.d, r.grid["height"], r.grid["width"]), device=dev)
+                t = srv.submit(pids[k], r.grid, out, None, basis=r.basis, h=r.h,
+                               precision=prec)
+                outs[t] = out
+                pending[t] = k
+                k += 1
+            for t in list(pending):
+                res = srv.poll(t)
+                if res is not None:
+                    assert res["status"] == 0, res
+                    lat.append(res["t_end"] - res["t_submit"])
+                    del pending[t], outs[t]
+            time.sleep(0.0002)
+        return time.perf_counter() - t0, np.array(lat)
+
+    out = {"metric": "MLS served fit requests: throughput and p50/p99 latency",
+           "unit": "requests/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "c4_256_requests_mixed", "requests": len(reqs),
+                      "slots": args.slots, "budget_bytes": budget,
+                      "pairs_total": int(sum(pairs))}}
+    for prec in ("fp16", "f64"):
+        run(prec)                                  # warm-up pass
+        wall, lat = run(prec)
+        rate = len(reqs) / wall
+        rec = {"saturation_requests_per_s": rate, "pairs_per_s": sum(pairs) / wall,
+               "closed_loop_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+               "closed_loop_p99_ms": 1e3 * float(np.percentile(lat, 99))}
+        for frac in (0.5, 0.8, 1.0):
+            arr = wl.poisson_arrivals(1, len(reqs), frac * rate)
+            wall2, lat2 = run(prec, arr)
+            rec[f"poisson_{frac}"] = {"offered_requests_per_s": frac * rate,
+                                      "achieved_requests_per_s": len(reqs) / wall2,
+                                      "p50_ms": 1e3 * float(np.percentile(lat2, 50)),
+                                      "p99_ms": 1e3 * float(np.percentile(lat2, 99))}
+        out[prec] = rec
+    out["value"] = out["fp16"]["saturation_requests_per_s"]
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2: the 1024^2 fit + contour step (default); c4: the served "
+                         "request mix with Poisson arrivals")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
@@ -67,42 +146,70 @@ def main():
     import torch
     from paper_1408_0677_amd import api, workloads as wl
 
+    if args.workload == "c4":
+        print(json.dumps(serve_bench(args)), flush=True)
+        return
+
     w = wl.c2()
     dev = torch.device("cuda:0")
     P = torch.from_numpy(w.points).to(dev)
     V = torch.from_numpy(w.values).to(dev)
+    iso = torch.from_numpy(w.iso()).to(dev)
     W, H = w.grid["width"], w.grid["height"]
     fields = torch.empty((w.d, H, W), dtype=torch.float32, device=dev)
     degree = torch.empty((H, W), dtype=torch.uint8, device=dev)
     ctx = api.default_context(0)
     stream = torch.cuda.current_stream()
 
-    def step():
+    # size the segment buffer once (outside the timed region)
+    api.fit(P, V, w.grid, basis=w.basis, h=w.h, out=fields, degree_out=degree, ctx=ctx,
+            stream=stream)
+    segs0, _, _ = api.contour(fields, w.grid, iso, ctx=ctx, stream=stream)
+    capacity = int(segs0.shape[0] * 1.25) + 1024
+    seg_count = int(segs0.shape[0])
+
+    fit_ev = []
+
+    def step(timed):
+        if timed:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
         api.fit(P, V, w.grid, basis=w.basis, h=w.h, out=fields, degree_out=degree,
                 ctx=ctx, stream=stream)
+        if timed:
+            b.record(stream)
+            fit_ev.append((a, b))
+        api.contour(fields, w.grid, iso, capacity=capacity, want_ids=True, ctx=ctx,
+                    stream=stream)
 
     for _ in range(args.warmup):
-        step()
+        step(False)
     torch.cuda.synchronize()
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    step_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s, e in ev:
-        s.record(stream)
-        step()
-        e.record(stream)
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        step(True)            # mls_contour returns after the stream has delivered its count
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_ms = np.array([s.elapsed_time(e) for s, e in ev])
+    step_ms = np.array(step_ms)
+    fit_ms = np.array([a.elapsed_time(b) for a, b in fit_ev])
+
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     nodes = W * H
     pairs = nodes * w.n
     F = moment_terms(w.basis) + basis_terms(w.basis) * w.d
     flops = 2.0 * F * pairs
     ms_per_step = wall * 1e3 / args.steps
-    kern_ms = float(np.mean(step_ms))   # one fit kernel launch per step
+    kern_ms = float(np.mean(fit_ms))   # one fit kernel launch per step
     achieved = flops / (kern_ms * 1e-3) / 1e12
 
     out = {
@@ -120,10 +227,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nodes": nodes, "points": w.n, "attributes": w.d,
                    "basis": w.basis, "weight": "gaussian", "h": w.h,
-                   "contraction": "f64 mfma", "solve": "f64"},
+                   "contraction": "f64 mfma", "solve": "f64", "isovalues_per_field": w.n_iso,
+                   "segments": seg_count},
         "fields_per_s": w.d * args.steps / wall,
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
-                       "p99": float(np.percentile(step_ms, 99))},
+                       "p99": float(np.percentile(step_ms, 99)),
+                       "fit_p50": float(np.percentile(fit_ms, 50)),
+                       "fit_p99": float(np.percentile(fit_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
                      "traffic": None, "kernel": "fit_f64_kernel",

@@ -51,7 +51,9 @@ typedef enum {
   MLS_ERR_OUT_OF_MEMORY = -2, /* a library scratch allocation failed */
   MLS_ERR_CAPACITY = -3,      /* output buffer too small (contour) */
   MLS_ERR_DEVICE = -4,        /* HIP runtime error, wrong device */
-  MLS_ERR_UNSUPPORTED = -7    /* valid request this build does not run */
+  MLS_ERR_OVER_BUDGET = -5,   /* (server) request or point set exceeds the budget */
+  MLS_ERR_UNSUPPORTED = -7,   /* valid request this build does not run */
+  MLS_PENDING = 1             /* (server) request not finished yet */
 } mls_status;
 
 typedef enum {
@@ -72,9 +74,17 @@ typedef enum {
  *  MLS_PREC_F64:  float64 contraction on the matrix cores.  This is the
  *                 accurate plain path: the normal equations lose about
  *                 log10(condition) digits, which float32 sums cannot spare.
+ *  MLS_PREC_BF16: bfloat16 matrix-core contraction with float32
+ *                 accumulation.  Attributes are normalised to [-1, 1], each
+ *                 feature is carried as `lp_terms` bfloat16 terms (default
+ *                 3, about 24 significant bits), the weight is rounded once
+ *                 per (node, point) and shared by all features.
+ *  MLS_PREC_FP16: the same with float16 terms.
  */
 typedef enum {
-  MLS_PREC_F64 = 0
+  MLS_PREC_F64 = 0,
+  MLS_PREC_BF16 = 1,
+  MLS_PREC_FP16 = 2
 } mls_precision;
 
 typedef struct {
@@ -94,6 +104,8 @@ typedef struct {
 typedef struct {
   double pivot_tol;     /* tau: smallest accepted equilibrated pivot; 1e-8 */
   double weight_floor;  /* nodes with sum of weights below this are NaN; 1e-6 */
+  int32_t lp_terms;     /* 16-bit terms per feature for MLS_PREC_BF16/FP16:
+                           1, 2 or 3; 0 selects 3 */
 } mls_solve_opts;
 
 typedef struct mls_context mls_context;
@@ -102,10 +114,14 @@ typedef struct mls_context mls_context;
 #define MLS_DEGREE_UNDETERMINED 255
 #define MLS_DEGREE_POINT_HIT 254
 
-/* Largest attribute count D accepted by mls_fit for each basis. */
+/* Largest attribute count D accepted by mls_fit with MLS_PREC_F64 for each
+ * basis, and with the 16-bit precisions (any basis). */
 #define MLS_MAX_D_CONSTANT 255
 #define MLS_MAX_D_LINEAR 83
 #define MLS_MAX_D_QUADRATIC 40
+#define MLS_MAX_D_LP 1024
+/* Largest point count. */
+#define MLS_MAX_N ((int64_t)1 << 31)
 
 /* Status name ("MLS_OK", ...); never NULL. */
 const char* mls_status_string(mls_status s);
@@ -124,7 +140,9 @@ void mls_context_destroy(mls_context* ctx);
  * Evaluate D MLS fields on a grid (Sec. 3.3, Eq. 4-8; see top of file).
  *  d_points  float32 [n][2] (x, y), row-major, device
  *  d_values  float32 [n][d], row-major, device
- *  n >= 1 points, 1 <= d <= MLS_MAX_D_<basis> attributes
+ *  n >= 1 points (at most MLS_MAX_N), 1 <= d attributes (at most
+ *            MLS_MAX_D_<basis> for MLS_PREC_F64, MLS_MAX_D_LP otherwise);
+ *            coordinates and values must be finite
  *  basis     mls_basis
  *  weight    weight kind and parameters (host struct)
  *  grid      grid description (host struct), width >= 1, height >= 1,
@@ -134,14 +152,32 @@ void mls_context_destroy(mls_context* ctx);
  *  d_fields  float32 [d][height][width] output, device
  *  d_degree  uint8 [height][width] output (accepted degree, 255 for
  *            undetermined), device, or NULL
- * Supported in this build: MLS_PREC_F64 with the Gaussian weight and all
- * three bases; other combinations return MLS_ERR_UNSUPPORTED.
+ * Supported in this build: the Gaussian weight with all three bases and all
+ * precisions; other combinations return MLS_ERR_UNSUPPORTED.  MLS_PREC_FP16
+ * also returns MLS_ERR_UNSUPPORTED when the grid spacing is so coarse
+ * against h that tile-frame features would leave the float16 range.
+ * The 16-bit precisions use library scratch of about 4 n d bytes.
  */
 mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
                    int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
                    const mls_grid* grid, int32_t precision,
                    const mls_solve_opts* opts, float* d_fields, uint8_t* d_degree,
                    void* stream);
+
+/*
+ * Device scratch bytes mls_fit needs for this request (0 for MLS_PREC_F64);
+ * 0 also for invalid arguments.
+ */
+size_t mls_fit_scratch_bytes(int64_t n, int32_t d, int32_t precision,
+                             const mls_weight* weight, const mls_grid* grid);
+
+/*
+ * Allocate `bytes` of fit scratch in the context now, so that later mls_fit
+ * calls that need at most that much allocate nothing.  (mls_fit grows the
+ * scratch when it needs more; growing frees the old buffer, which waits for
+ * the device.)
+ */
+mls_status mls_context_reserve(mls_context* ctx, size_t bytes);
 
 /*
  * Marching-squares contour lines of fields on a grid (Sec. 3.4, contour
@@ -175,6 +211,63 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
                        const mls_grid* grid, const float* d_iso, int32_t n_iso,
                        uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
                        int64_t capacity, int64_t* h_count, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Served form: resident point sets and continuously batched fit requests    */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper re-evaluates the MLS field on every interaction (Sec. 3.5,
+ * Sec. 4.5).  A server keeps point sets resident on one device and runs fit
+ * requests as they arrive: a scheduler thread admits queued requests in
+ * arrival order onto `slots` execution slots (a stream and a context with
+ * reserved scratch each), so requests overlap on the device and a request
+ * that arrives while others run starts as soon as a slot is free.  Memory:
+ * resident point sets + slots x slot_scratch_bytes <= hbm_budget_bytes;
+ * admitted requests allocate nothing.  All server calls are thread-safe.
+ * Results of a request are bit-identical whether it runs alone or among
+ * others.  Timestamps are seconds since server creation (steady clock).
+ */
+typedef struct mls_server mls_server;
+
+typedef struct {
+  uint64_t pointset;      /* id from mls_server_put_points */
+  int32_t basis;          /* mls_basis */
+  mls_weight weight;
+  mls_grid grid;
+  int32_t precision;      /* mls_precision */
+  mls_solve_opts opts;    /* zeros select nothing useful: set tau, floor */
+  float* d_fields;        /* [d][height][width] output, caller-owned device */
+  uint8_t* d_degree;      /* [height][width] output or NULL */
+} mls_request;
+
+typedef struct {
+  int32_t status;         /* MLS_PENDING, MLS_OK or the fit's error status */
+  double t_submit, t_admit, t_start, t_end;
+  char detail[128];       /* error detail */
+} mls_result;
+
+/* Create a server on `device` with `slots` execution slots (1..64) of
+ * `slot_scratch_bytes` reserved scratch each (see mls_fit_scratch_bytes). */
+mls_status mls_server_create(int32_t device, size_t hbm_budget_bytes, int32_t slots,
+                             size_t slot_scratch_bytes, mls_server** out);
+/* Wait for all submitted requests, then free everything. */
+void mls_server_destroy(mls_server* srv);
+/* Copy a point set (device or host pointers) into server memory. */
+mls_status mls_server_put_points(mls_server* srv, const float* points, const float* values,
+                                 int64_t n, int32_t d, uint64_t* pointset);
+/* Drop a point set once no queued or running request uses it. */
+mls_status mls_server_release_points(mls_server* srv, uint64_t pointset);
+/* Queue a request (returns at once).  MLS_ERR_OVER_BUDGET if its scratch
+ * exceeds a slot's; argument errors of the fit itself surface in its
+ * result. */
+mls_status mls_server_submit(mls_server* srv, const mls_request* req, uint64_t* ticket);
+/* MLS_PENDING while the request runs; MLS_OK once finished (the result is
+ * written, the ticket retired; result.status holds the fit's status). */
+mls_status mls_server_poll(mls_server* srv, uint64_t ticket, mls_result* out);
+/* Block until the request finishes, then as mls_server_poll. */
+mls_status mls_server_wait(mls_server* srv, uint64_t ticket, mls_result* out);
+/* Detail of the calling thread's last failed server call. */
+const char* mls_server_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -5,4 +5,5 @@ Eq. 4-8) on a grid over scattered points with D attributes, in hand-written
 HIP kernels behind a C ABI (include/mls.h).  The Python layer only marshals
 arguments: see :mod:`paper_1408_0677_amd.api`.
 """
-from .api import (BASIS, PRECISION, WEIGHT, MlsError, Context, contour, fit)  # noqa: F401
+from .api import (BASIS, PRECISION, WEIGHT, MlsError, Context, Server, ServerError,  # noqa: F401
+                  contour, fit, fit_scratch_bytes)

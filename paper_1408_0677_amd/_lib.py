@@ -15,7 +15,10 @@ LIB_PATH = os.environ.get("MLS_HIP_LIB") or os.path.join(HERE, "libmls_hip.so")
 
 # Symbols declared in include/mls.h.
 EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
-           "mls_context_destroy", "mls_fit", "mls_contour")
+           "mls_context_destroy", "mls_fit", "mls_contour", "mls_fit_scratch_bytes",
+           "mls_context_reserve", "mls_server_create", "mls_server_destroy",
+           "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
+           "mls_server_poll", "mls_server_wait", "mls_server_last_error")
 
 
 class MlsGrid(ctypes.Structure):
@@ -30,7 +33,21 @@ class MlsWeight(ctypes.Structure):
 
 
 class MlsSolveOpts(ctypes.Structure):
-    _fields_ = [("pivot_tol", ctypes.c_double), ("weight_floor", ctypes.c_double)]
+    _fields_ = [("pivot_tol", ctypes.c_double), ("weight_floor", ctypes.c_double),
+                ("lp_terms", ctypes.c_int32)]
+
+
+class MlsRequest(ctypes.Structure):
+    _fields_ = [("pointset", ctypes.c_uint64), ("basis", ctypes.c_int32),
+                ("weight", MlsWeight), ("grid", MlsGrid), ("precision", ctypes.c_int32),
+                ("opts", MlsSolveOpts), ("d_fields", ctypes.c_void_p),
+                ("d_degree", ctypes.c_void_p)]
+
+
+class MlsResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_end", ctypes.c_double), ("detail", ctypes.c_char * 128)]
 
 
 _lib = None
@@ -62,5 +79,28 @@ def load():
     lib.mls_contour.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P, i64,
                                 ctypes.POINTER(i64), P]
     lib.mls_contour.restype = ctypes.c_int
+    lib.mls_fit_scratch_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(MlsWeight),
+                                          ctypes.POINTER(MlsGrid)]
+    lib.mls_fit_scratch_bytes.restype = ctypes.c_size_t
+    lib.mls_context_reserve.argtypes = [P, ctypes.c_size_t]
+    lib.mls_context_reserve.restype = ctypes.c_int
+    lib.mls_server_create.argtypes = [i32, ctypes.c_size_t, i32, ctypes.c_size_t,
+                                      ctypes.POINTER(P)]
+    lib.mls_server_create.restype = ctypes.c_int
+    lib.mls_server_destroy.argtypes = [P]
+    lib.mls_server_destroy.restype = None
+    lib.mls_server_put_points.argtypes = [P, P, P, i64, i32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.mls_server_put_points.restype = ctypes.c_int
+    lib.mls_server_release_points.argtypes = [P, ctypes.c_uint64]
+    lib.mls_server_release_points.restype = ctypes.c_int
+    lib.mls_server_submit.argtypes = [P, ctypes.POINTER(MlsRequest),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    lib.mls_server_submit.restype = ctypes.c_int
+    lib.mls_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(MlsResult)]
+    lib.mls_server_poll.restype = ctypes.c_int
+    lib.mls_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(MlsResult)]
+    lib.mls_server_wait.restype = ctypes.c_int
+    lib.mls_server_last_error.argtypes = []
+    lib.mls_server_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib

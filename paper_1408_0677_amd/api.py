@@ -12,7 +12,7 @@ from . import _lib
 
 BASIS = {"constant": 0, "linear": 1, "quadratic": 2}
 WEIGHT = {"gaussian": 0, "wendland": 1, "invpow": 2}
-PRECISION = {"f64": 0}
+PRECISION = {"f64": 0, "bf16": 1, "fp16": 2}
 STATUS_OK = 0
 DEGREE_UNDETERMINED = 255
 
@@ -86,7 +86,7 @@ def _stream_handle(stream):
 
 def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussian",
         h: float = 0.05, alpha: float = 1.0, precision: str = "f64",
-        pivot_tol: float = 1e-8, weight_floor: float = 1e-6, out=None,
+        pivot_tol: float = 1e-8, weight_floor: float = 1e-6, lp_terms: int = 0, out=None,
         degree_out=None, want_degree: bool = True, ctx: Context | None = None,
         stream=None):
     """MLS fields of ``values`` (N, D) at the nodes of ``grid``.
@@ -109,7 +109,7 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
     ctx = ctx or default_context(points.device.index)
     g = grid_struct(grid)
     wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
-    opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor))
+    opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor), int(lp_terms))
     st = _lib.load().mls_fit(ctx.handle, _ptr(points), _ptr(values), n, d, BASIS[basis],
                              ctypes.byref(wt), ctypes.byref(g), PRECISION[precision],
                              ctypes.byref(opts), _ptr(out), _ptr(degree_out),
@@ -159,3 +159,109 @@ def contour(fields, grid: dict, iso, want_cases: bool = True, want_ids: bool = T
         break
     n = int(count.value)
     return segs[:n], (ids[:n] if ids is not None else None), cases
+
+
+PENDING = 1
+
+
+def fit_scratch_bytes(n: int, d: int, grid: dict, precision: str = "f64",
+                      weight: str = "gaussian", h: float = 0.05, alpha: float = 1.0) -> int:
+    """Device scratch bytes mls_fit needs for such a request."""
+    wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
+    return int(_lib.load().mls_fit_scratch_bytes(int(n), int(d), PRECISION[precision],
+                                                 ctypes.byref(wt),
+                                                 ctypes.byref(grid_struct(grid))))
+
+
+class ServerError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _lib.load()
+        name = lib.mls_status_string(status).decode()
+        super().__init__(f"{where}: {name}: {lib.mls_server_last_error().decode()}")
+        self.status = status
+        self.name = name
+
+
+class Server:
+    """The served form (mls_server_*): resident point sets, requests admitted
+    onto concurrent slots as they arrive.  Output tensors of submitted
+    requests must stay alive until their result is collected."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 2 << 30, slots: int = 4,
+                 slot_scratch: int = 64 << 20):
+        self._ptr = ctypes.c_void_p()
+        st = _lib.load().mls_server_create(int(device), int(hbm_budget), int(slots),
+                                           int(slot_scratch), ctypes.byref(self._ptr))
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_create")
+        self._keep = {}
+
+    def close(self):
+        if self._ptr:
+            _lib.load().mls_server_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def put_points(self, points, values) -> int:
+        if values.dim() == 1:
+            values = values.view(-1, 1)
+        pid = ctypes.c_uint64()
+        st = _lib.load().mls_server_put_points(self._ptr, _ptr(points.contiguous()),
+                                               _ptr(values.contiguous()), values.shape[0],
+                                               values.shape[1], ctypes.byref(pid))
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_put_points")
+        return int(pid.value)
+
+    def release_points(self, pointset: int):
+        st = _lib.load().mls_server_release_points(self._ptr, int(pointset))
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_release_points")
+
+    def submit(self, pointset: int, grid: dict, out, degree_out=None, basis: str = "linear",
+               weight: str = "gaussian", h: float = 0.05, alpha: float = 1.0,
+               precision: str = "f64", pivot_tol: float = 1e-8, weight_floor: float = 1e-6,
+               lp_terms: int = 0) -> int:
+        req = _lib.MlsRequest(int(pointset), BASIS[basis],
+                              _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha)),
+                              grid_struct(grid), PRECISION[precision],
+                              _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor),
+                                                int(lp_terms)),
+                              out.data_ptr(),
+                              None if degree_out is None else degree_out.data_ptr())
+        t = ctypes.c_uint64()
+        st = _lib.load().mls_server_submit(self._ptr, ctypes.byref(req), ctypes.byref(t))
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_submit")
+        self._keep[int(t.value)] = (out, degree_out)
+        return int(t.value)
+
+    @staticmethod
+    def _result(res):
+        return {"status": int(res.status), "t_submit": res.t_submit, "t_admit": res.t_admit,
+                "t_start": res.t_start, "t_end": res.t_end, "detail": res.detail.decode()}
+
+    def poll(self, ticket: int):
+        """None while pending, else the result dict."""
+        res = _lib.MlsResult()
+        st = _lib.load().mls_server_poll(self._ptr, int(ticket), ctypes.byref(res))
+        if st == PENDING:
+            return None
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_poll")
+        self._keep.pop(int(ticket), None)
+        return self._result(res)
+
+    def wait(self, ticket: int):
+        res = _lib.MlsResult()
+        st = _lib.load().mls_server_wait(self._ptr, int(ticket), ctypes.byref(res))
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_wait")
+        self._keep.pop(int(ticket), None)
+        return self._result(res)

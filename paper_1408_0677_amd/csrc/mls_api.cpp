@@ -12,11 +12,18 @@
 #include "../../include/mls.h"
 #include "mls_internal.h"
 
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
 struct mls_context {
   int device;
-  // device scratch, grown on demand (contour counts, offsets, tile sums)
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
+  // device scratch, grown on demand: contour counts, offsets, tile sums
+  Scratch scratch;
+  // fit staging: attribute ranges, shift/scale, normalised values
+  Scratch fit_scratch;
+
   // pinned host word for counts read back by mls_contour
   int64_t* pinned = nullptr;
 };
@@ -63,29 +70,96 @@ mls_status check_device_ptr(const mls_context* ctx, const void* ptr, const char*
   return MLS_OK;
 }
 
-// Make sure ctx->scratch holds at least `bytes`.
-mls_status ensure_scratch(mls_context* ctx, size_t bytes) {
-  if (ctx->scratch_bytes >= bytes) return MLS_OK;
-  if (ctx->scratch) {
-    hipError_t e = hipFree(ctx->scratch);  // synchronises with queued work
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
+// Make sure `sc` holds at least `bytes`.
+mls_status ensure_scratch(Scratch& sc, size_t bytes) {
+  if (sc.bytes >= bytes) return MLS_OK;
+  if (sc.ptr) {
+    hipError_t e = hipFree(sc.ptr);  // synchronises with queued work
+    sc.ptr = nullptr;
+    sc.bytes = 0;
     if (e != hipSuccess) return device_fail(e, "hipFree");
   }
   size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
-  hipError_t e = hipMalloc(&ctx->scratch, want);
+  hipError_t e = hipMalloc(&sc.ptr, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    ctx->scratch = nullptr;
+    sc.ptr = nullptr;
     return fail(MLS_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes failed", want);
   }
-  ctx->scratch_bytes = want;
+  sc.bytes = want;
   return MLS_OK;
 }
 
+}  // namespace
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-}  // namespace
+namespace mls {
+
+// Device scratch layout of one mls_fit call (none for the float64 path).
+FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, double h,
+                      double x0, double y0, double dx, double dy, int32_t W, int32_t H) {
+  FitPlan p{};
+  if (precision == MLS_PREC_F64) return p;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes, 256);
+    return o;
+  };
+  const int64_t nblk = stage_partial_blocks(n);
+  p.o_pmin = carve(sizeof(float) * (size_t)(nblk * d));
+  p.o_pmax = carve(sizeof(float) * (size_t)(nblk * d));
+  p.o_shift = carve(sizeof(float) * (size_t)d);
+  p.o_scale = carve(sizeof(float) * (size_t)d);
+  p.o_vals = carve(sizeof(float) * (size_t)n * (size_t)d);
+  if (wkind == MLS_W_WENDLAND_C2) {
+    // cells of side >= h over the grid extent grown by h (points outside it
+    // fall into the border cells, which is still exact: the weight decides,
+    // the cells only bound the search)
+    const double xa = x0, xb = x0 + (double)(W - 1) * dx;
+    const double ya = y0, yb = y0 + (double)(H - 1) * dy;
+    const double xmin = std::fmin(xa, xb), xmax = std::fmax(xa, xb);
+    const double ymin = std::fmin(ya, yb), ymax = std::fmax(ya, yb);
+    const double wx = (xmax - xmin) + 2.0 * h, wy = (ymax - ymin) + 2.0 * h;
+    p.geom.cell = std::fmax(h, std::fmax(wx, wy) / 2048.0);
+    p.geom.ox = xmin - h;
+    p.geom.oy = ymin - h;
+    p.geom.x0 = x0;
+    p.geom.y0 = y0;
+    p.geom.dx = dx;
+    p.geom.dy = dy;
+    p.geom.h = h;
+    p.ncx = (int)std::floor(wx / p.geom.cell) + 1;
+    p.ncy = (int)std::floor(wy / p.geom.cell) + 1;
+    p.tiles_x = (W + kTileCols - 1) / kTileCols;
+    p.tiles = p.tiles_x * ((H + kTileRows - 1) / kTileRows);
+    const int64_t ncells = (int64_t)p.ncx * p.ncy;
+    const int64_t nrb = radix_blocks(n), trb = radix_blocks(p.tiles);
+    p.o_keys = carve(4 * (size_t)n);
+    p.o_keys2 = carve(4 * (size_t)n);
+    p.o_perm = carve(4 * (size_t)n);
+    p.o_perm2 = carve(4 * (size_t)n);
+    p.o_hist = carve(4 * 256 * (size_t)nrb);
+    p.o_cs = carve(4 * (size_t)(ncells + 1));
+    p.o_pts = carve(8 * (size_t)n);
+    p.o_vals_s = carve(4 * (size_t)n * (size_t)d);
+    p.o_tk = carve(4 * (size_t)p.tiles);
+    p.o_tk2 = carve(4 * (size_t)p.tiles);
+    p.o_to = carve(4 * (size_t)p.tiles);
+    p.o_to2 = carve(4 * (size_t)p.tiles);
+    p.o_th = carve(4 * 256 * (size_t)trb);
+  }
+  p.total = off;
+  return p;
+}
+
+size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t precision, int32_t wkind, double h,
+                         double x0, double y0, double dx, double dy, int32_t W, int32_t H) {
+  return make_fit_plan(n, d, precision, wkind, h, x0, y0, dx, dy, W, H).total;
+}
+
+}  // namespace mls
 
 extern "C" {
 
@@ -96,7 +170,9 @@ const char* mls_status_string(mls_status s) {
     case MLS_ERR_OUT_OF_MEMORY: return "MLS_ERR_OUT_OF_MEMORY";
     case MLS_ERR_CAPACITY: return "MLS_ERR_CAPACITY";
     case MLS_ERR_DEVICE: return "MLS_ERR_DEVICE";
+    case MLS_ERR_OVER_BUDGET: return "MLS_ERR_OVER_BUDGET";
     case MLS_ERR_UNSUPPORTED: return "MLS_ERR_UNSUPPORTED";
+    case MLS_PENDING: return "MLS_PENDING";
   }
   return "MLS_UNKNOWN_STATUS";
 }
@@ -128,7 +204,9 @@ mls_status mls_context_create(int32_t device, mls_context** out) {
 void mls_context_destroy(mls_context* ctx) {
   if (!ctx) return;
   if (hipSetDevice(ctx->device) == hipSuccess) {
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->scratch.ptr) (void)hipFree(ctx->scratch.ptr);
+    if (ctx->fit_scratch.ptr) (void)hipFree(ctx->fit_scratch.ptr);
+
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   }
   delete ctx;
@@ -143,10 +221,13 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   if (basis < MLS_BASIS_CONSTANT || basis > MLS_BASIS_QUADRATIC)
     return fail(MLS_ERR_INVALID_ARG, "basis %d is not an mls_basis", basis);
   if (n < 1) return fail(MLS_ERR_INVALID_ARG, "n = %lld; need at least one point", (long long)n);
-  if (n > (int64_t)1 << 40) return fail(MLS_ERR_INVALID_ARG, "n = %lld is too large", (long long)n);
-  if (d < 1 || d > max_d_for(basis))
-    return fail(MLS_ERR_INVALID_ARG, "d = %d; basis %d accepts 1..%d attributes", d, basis,
-                max_d_for(basis));
+  if (n > MLS_MAX_N) return fail(MLS_ERR_INVALID_ARG, "n = %lld is too large", (long long)n);
+  if (precision < MLS_PREC_F64 || precision > MLS_PREC_FP16)
+    return fail(MLS_ERR_INVALID_ARG, "precision %d is not an mls_precision", precision);
+  const int dmax = precision == MLS_PREC_F64 ? max_d_for(basis) : MLS_MAX_D_LP;
+  if (d < 1 || d > dmax)
+    return fail(MLS_ERR_INVALID_ARG, "d = %d; basis %d with precision %d accepts 1..%d attributes",
+                d, basis, precision, dmax);
   if (!weight) return fail(MLS_ERR_INVALID_ARG, "weight is NULL");
   if (weight->kind < MLS_W_GAUSSIAN || weight->kind > MLS_W_INVPOW)
     return fail(MLS_ERR_INVALID_ARG, "weight kind %d is not an mls_weight_kind", weight->kind);
@@ -163,12 +244,14 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
                 grid->height);
   if (!is_finite(grid->x0) || !is_finite(grid->y0) || !is_finite(grid->dx) || !is_finite(grid->dy))
     return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
-  if (precision != MLS_PREC_F64)
-    return fail(MLS_ERR_INVALID_ARG, "precision %d is not an mls_precision", precision);
   double tau = 1e-8, floor_w = 1e-6;
+  int terms = 3;
   if (opts) {
     tau = opts->pivot_tol;
     floor_w = opts->weight_floor;
+    if (opts->lp_terms < 0 || opts->lp_terms > 3)
+      return fail(MLS_ERR_INVALID_ARG, "lp_terms = %d; need 0..3", opts->lp_terms);
+    if (opts->lp_terms > 0) terms = opts->lp_terms;
     if (!is_finite(tau) || !(tau > 0.0) || !(tau <= 1.0))
       return fail(MLS_ERR_INVALID_ARG, "pivot_tol = %g; need 0 < tau <= 1", tau);
     if (!is_finite(floor_w) || floor_w < 0.0)
@@ -178,7 +261,8 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   if (!d_values) return fail(MLS_ERR_INVALID_ARG, "d_values is NULL");
   if (!d_fields) return fail(MLS_ERR_INVALID_ARG, "d_fields is NULL");
   if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
-  if (weight->kind != MLS_W_GAUSSIAN)
+  if (weight->kind == MLS_W_INVPOW ||
+      (weight->kind == MLS_W_WENDLAND_C2 && precision == MLS_PREC_F64))
     return fail(MLS_ERR_UNSUPPORTED, "weight kind %d is not available with precision %d",
                 weight->kind, precision);
 
@@ -210,9 +294,93 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   a.floor_w = floor_w;
   a.fields = d_fields;
   a.deg_out = d_degree;
-  e = mls::launch_fit_f64(a, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == MLS_PREC_F64) {
+    e = mls::launch_fit_f64(a, s);
+    if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+    return MLS_OK;
+  }
+  const bool fp16 = precision == MLS_PREC_FP16;
+  if (fp16) {
+    // tile-frame features reach |u| <= 8 + half the tile diagonal (in h);
+    // the largest, u^4 times an attribute in [-1, 1], must stay finite
+    const double sx = grid->dx / weight->h, sy = grid->dy / weight->h;
+    const double reach = 8.0 + 0.5 * std::sqrt(256.0 * (sx * sx + sy * sy));
+    const double big = basis == MLS_BASIS_QUADRATIC ? reach * reach * reach * reach
+                       : (basis == MLS_BASIS_LINEAR ? reach * reach : 1.0);
+    if (big > 6.0e4)
+      return fail(MLS_ERR_UNSUPPORTED, "grid spacing %g x %g is too coarse against h = %g for "
+                  "float16 features", grid->dx, grid->dy, weight->h);
+  }
+  const mls::FitPlan plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h,
+                                               grid->x0, grid->y0, grid->dx, grid->dy,
+                                               grid->width, grid->height);
+  if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
+  char* base = (char*)ctx->fit_scratch.ptr;
+  float* pmin = (float*)(base + plan.o_pmin);
+  float* pmax = (float*)(base + plan.o_pmax);
+  float* shift = (float*)(base + plan.o_shift);
+  float* scale = (float*)(base + plan.o_scale);
+  float* vals_t = (float*)(base + plan.o_vals);
+  e = mls::launch_stage(d_values, n, d, pmin, pmax, shift, scale, vals_t, s);
+  if (e != hipSuccess) return device_fail(e, "staging kernel launch");
+  if (weight->kind != MLS_W_WENDLAND_C2) {
+    e = mls::launch_fit_lp(a, vals_t, shift, scale, fp16, terms, nullptr, s);
+    if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+    return MLS_OK;
+  }
+  mls::CellArgs ca;
+  ca.pts = d_points;
+  ca.vals_t = vals_t;
+  ca.n = n;
+  ca.D = d;
+  ca.geom = plan.geom;
+  ca.ncx = plan.ncx;
+  ca.ncy = plan.ncy;
+  ca.tiles_x = plan.tiles_x;
+  ca.tiles = plan.tiles;
+  ca.cell_start = (uint32_t*)(base + plan.o_cs);
+  ca.perm = (uint32_t*)(base + plan.o_perm);
+  ca.pts_s = (float*)(base + plan.o_pts);
+  ca.vals_ts = (float*)(base + plan.o_vals_s);
+  ca.torder = (uint32_t*)(base + plan.o_to);
+  ca.keys = (uint32_t*)(base + plan.o_keys);
+  ca.keys2 = (uint32_t*)(base + plan.o_keys2);
+  ca.perm2 = (uint32_t*)(base + plan.o_perm2);
+  ca.hist = (uint32_t*)(base + plan.o_hist);
+  ca.tkeys = (uint32_t*)(base + plan.o_tk);
+  ca.tkeys2 = (uint32_t*)(base + plan.o_tk2);
+  ca.torder2 = (uint32_t*)(base + plan.o_to2);
+  ca.thist = (uint32_t*)(base + plan.o_th);
+  e = mls::launch_cells(ca, s);
+  if (e != hipSuccess) return device_fail(e, "cell list kernels");
+  mls::LPCells cl;
+  cl.pts_s = ca.pts_s;
+  cl.vals_ts = ca.vals_ts;
+  cl.cell_start = ca.cell_start;
+  cl.torder = ca.torder;
+  cl.ncx = plan.ncx;
+  cl.ncy = plan.ncy;
+  cl.geom = plan.geom;
+  e = mls::launch_fit_lp(a, vals_t, shift, scale, fp16, terms, &cl, s);
   if (e != hipSuccess) return device_fail(e, "fit kernel launch");
   return MLS_OK;
+}
+
+mls_status mls_context_reserve(mls_context* ctx, size_t bytes) {
+  g_last_error[0] = '\0';
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  return ensure_scratch(ctx->fit_scratch, bytes);
+}
+
+size_t mls_fit_scratch_bytes(int64_t n, int32_t d, int32_t precision, const mls_weight* weight,
+                             const mls_grid* grid) {
+  if (!weight || !grid || n < 1 || d < 1) return 0;
+  return mls::make_fit_plan(n, d, precision, weight->kind, weight->h, grid->x0, grid->y0,
+                            grid->dx, grid->dy, grid->width, grid->height)
+      .total;
 }
 
 mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
@@ -259,7 +427,7 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
   const size_t off_tiles = off_offsets + align_up(sizeof(int64_t) * (size_t)entries, 256);
   const size_t off_total = off_tiles + align_up(sizeof(int64_t) * (size_t)tiles, 256);
   const size_t need = off_total + 256;
-  if ((st = ensure_scratch(ctx, need)) != MLS_OK) return st;
+  if ((st = ensure_scratch(ctx->scratch, need)) != MLS_OK) return st;
   if (!ctx->pinned) {
     e = hipHostMalloc((void**)&ctx->pinned, sizeof(int64_t) * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -268,7 +436,7 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
       return fail(MLS_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
     }
   }
-  char* base = (char*)ctx->scratch;
+  char* base = (char*)ctx->scratch.ptr;
   mls::ContourArgs a;
   a.fields = d_fields;
   a.iso = d_iso;

@@ -30,6 +30,108 @@ __host__ __device__ constexpr int moment_terms(int deg) { return deg == 0 ? 1 : 
 // Float64 matrix-core fit (Gaussian weight).  Returns a hipError_t.
 hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream);
 
+// Cell-ordered payload for compactly supported weights (from launch_cells).
+struct CellGeom;
+struct LPCells;
+
+// 16-bit matrix-core fit (bf16 or fp16 feature terms, float32
+// accumulation).  vals_t/shift/scale come from launch_stage; the Wendland
+// weight needs `cells`.
+hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shift,
+                         const float* scale, bool fp16, int terms, const LPCells* cells,
+                         hipStream_t stream);
+void lp_slab_plan(int degree, int D, int* nts, int* ds, int* nslab);
+
+// Attribute staging: partial ranges (stage_partial_blocks(n) x D floats in
+// pmin and pmax), shift/scale [D], attribute-major normalised copy [D][n].
+int64_t stage_partial_blocks(int64_t n);
+hipError_t launch_stage(const float* vals, int64_t n, int D, float* pmin, float* pmax,
+                        float* shift, float* scale, float* vals_t, hipStream_t s);
+
+// Geometry shared by the cell list and the kernels that walk it: square
+// cells of side `cell` from (ox, oy); node tiles of kTileCols x kTileRows
+// nodes of the grid (x0 + c dx, y0 + r dy); support radius h.
+constexpr int kTileCols = 16;
+constexpr int kTileRows = 16;
+struct CellGeom {
+  double ox, oy, cell;
+  double x0, y0, dx, dy;
+  double h;
+};
+
+// Cell columns [cx0, cx1] and rows [cy0, cy1] that can hold points within h
+// of some node of tile (tc, tr).
+__host__ __device__ inline void tile_cell_range(const CellGeom& g, int tc, int tr, int ncx,
+                                                int ncy, int* cx0, int* cx1, int* cy0,
+                                                int* cy1) {
+  const double xa = g.x0 + (double)(tc * kTileCols) * g.dx;
+  const double xb = g.x0 + (double)(tc * kTileCols + kTileCols - 1) * g.dx;
+  const double ya = g.y0 + (double)(tr * kTileRows) * g.dy;
+  const double yb = g.y0 + (double)(tr * kTileRows + kTileRows - 1) * g.dy;
+  const double xlo = (xa < xb ? xa : xb) - g.h, xhi = (xa < xb ? xb : xa) + g.h;
+  const double ylo = (ya < yb ? ya : yb) - g.h, yhi = (ya < yb ? yb : ya) + g.h;
+  double fx0 = floor((xlo - g.ox) / g.cell), fx1 = floor((xhi - g.ox) / g.cell);
+  double fy0 = floor((ylo - g.oy) / g.cell), fy1 = floor((yhi - g.oy) / g.cell);
+  fx0 = fx0 < 0 ? 0 : fx0;
+  fy0 = fy0 < 0 ? 0 : fy0;
+  fx1 = fx1 > ncx - 1 ? ncx - 1 : fx1;
+  fy1 = fy1 > ncy - 1 ? ncy - 1 : fy1;
+  *cx0 = (int)fx0;
+  *cx1 = (int)fx1;
+  *cy0 = (int)fy0;
+  *cy1 = (int)fy1;
+}
+
+struct CellArgs {
+  const float* pts;        // [n][2]
+  const float* vals_t;     // [D][n] staged attributes
+  int64_t n;
+  int D;
+  CellGeom geom;
+  int ncx, ncy;
+  int tiles_x, tiles;
+  // outputs
+  uint32_t* cell_start;    // [ncx * ncy + 1]
+  uint32_t* perm;          // [n] input index of each sorted point
+  float* pts_s;            // [n][2] in cell order
+  float* vals_ts;          // [D][n] in cell order
+  uint32_t* torder;        // [tiles] node tiles by descending work
+  // scratch
+  uint32_t* keys;          // [n]
+  uint32_t* keys2;         // [n]
+  uint32_t* perm2;         // [n]
+  uint32_t* hist;          // [256 * radix_blocks(n)]
+  uint32_t* tkeys;         // [tiles]
+  uint32_t* tkeys2;        // [tiles]
+  uint32_t* torder2;       // [tiles]
+  uint32_t* thist;         // [256 * radix_blocks(tiles)]
+};
+int64_t radix_blocks(int64_t n);
+hipError_t launch_cells(const CellArgs& a, hipStream_t stream);
+
+// Scratch layout of one mls_fit call (byte offsets into one buffer).
+struct FitPlan {
+  size_t o_pmin, o_pmax, o_shift, o_scale, o_vals;
+  size_t o_keys, o_keys2, o_perm, o_perm2, o_hist, o_cs, o_pts, o_vals_s;
+  size_t o_tk, o_tk2, o_to, o_to2, o_th;
+  size_t total;
+  int ncx, ncy, tiles_x, tiles;
+  CellGeom geom;
+};
+FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, double h,
+                      double x0, double y0, double dx, double dy, int32_t W, int32_t H);
+size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t precision, int32_t wkind, double h,
+                         double x0, double y0, double dx, double dy, int32_t W, int32_t H);
+
+struct LPCells {
+  const float* pts_s;
+  const float* vals_ts;
+  const uint32_t* cell_start;
+  const uint32_t* torder;
+  int ncx, ncy;
+  CellGeom geom;
+};
+
 // Marching squares over D fields at n_iso isovalues each.
 struct ContourArgs {
   const float* fields;   // [D][H][W]

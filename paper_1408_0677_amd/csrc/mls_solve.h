@@ -47,15 +47,20 @@ __device__ __forceinline__ double shift_entry(int r, int c, double ex, double ey
 }
 
 // Solve one node.  `g` points at the node's F accumulated features
-// (consecutive doubles), `ex, ey` is delta.  Writes field_d to
-// fields[d * plane] (float32) and returns the accepted degree code.
-template <int DEG>
-__device__ uint8_t solve_node(const double* g, int D, double ex, double ey,
+// (consecutive values, float64 or float32), `ex, ey` is delta.  Writes
+// field_d to fields[d * plane] (float32) and returns the accepted degree
+// code.  If `shift` is given, the attributes were fitted as
+// (f_d - shift[d]) / scale[d] and the value is mapped back.  `wscale`
+// divides the weight sum before the floor test (weights that were scaled
+// by a common factor).
+template <int DEG, typename Acc>
+__device__ uint8_t solve_node(const Acc* g, int D, double ex, double ey,
                               double tau, double floor_w, float* fields,
-                              int64_t plane) {
+                              int64_t plane, const float* shift = nullptr,
+                              const float* scale = nullptr, double wscale = 1.0) {
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
   constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
-  const double sumw = g[0];
+  const double sumw = (double)g[0] / wscale;
   if (!(sumw >= floor_w)) {
     for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
     return 255;
@@ -65,7 +70,7 @@ __device__ uint8_t solve_node(const double* g, int D, double ex, double ey,
   for (int j = 0; j < m; ++j)
 #pragma unroll
     for (int k = 0; k < m; ++k)
-      Mt[j][k] = g[mono_index(basis_ax(j) + basis_ax(k), basis_ay(j) + basis_ay(k))];
+      Mt[j][k] = (double)g[mono_index(basis_ax(j) + basis_ax(k), basis_ay(j) + basis_ay(k))];
   double T[m][m];
 #pragma unroll
   for (int r = 0; r < m; ++r)
@@ -165,11 +170,12 @@ __device__ uint8_t solve_node(const double* g, int D, double ex, double ey,
     for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
     return 255;
   }
-  const double* R = g + nmom;
+  const Acc* R = g + nmom;
   for (int d = 0; d < D; ++d) {
     double v = 0.0;
 #pragma unroll
-    for (int c = 0; c < m; ++c) v += y[c] * R[c * D + d];
+    for (int c = 0; c < m; ++c) v += y[c] * (double)R[c * D + d];
+    if (shift) v = (double)shift[d] + (double)scale[d] * v;
     fields[(int64_t)d * plane] = (float)v;
   }
   return (uint8_t)accepted;

@@ -67,8 +67,10 @@ def _fit(lib, n=10, d=2, basis=1, kind=0, h=0.1, alpha=1.0, grid=(0.0, 0.0, 0.1,
     (dict(grid=(0.0, 0.0, 0.1, 0.1, 0, 8)), b"need width"),
     (dict(grid=(float("nan"), 0.0, 0.1, 0.1, 8, 8)), b"finite"),
     (dict(precision=9), b"precision 9"),
-    (dict(opts=(0.0, 1e-6)), b"pivot_tol"),
-    (dict(opts=(1e-8, -1.0)), b"weight_floor"),
+    (dict(precision=1, d=1025), b"d = 1025"),
+    (dict(opts=(0.0, 1e-6, 0)), b"pivot_tol"),
+    (dict(opts=(1e-8, -1.0, 0)), b"weight_floor"),
+    (dict(opts=(1e-8, 1e-6, 4)), b"lp_terms"),
     (dict(pts=0), b"d_points is NULL"),
     (dict(vals=0), b"d_values is NULL"),
     (dict(fields=0), b"d_fields is NULL"),
@@ -116,3 +118,34 @@ def test_contour_invalid_arguments(lib, kwargs, needle):
     assert st == -1, (st, lib.mls_last_error())
     assert needle in lib.mls_last_error(), lib.mls_last_error()
     assert cnt == -7          # nothing written on rejection
+
+
+def test_fit_scratch_plan(lib):
+    """Host-only scratch plan: none for float64, staging for 16-bit paths,
+    more with the cell list."""
+    from paper_1408_0677_amd import api
+    grid = {"x0": 0.0, "y0": 0.0, "dx": 0.01, "dy": 0.01, "width": 100, "height": 100}
+    assert api.fit_scratch_bytes(1000, 4, grid, "f64") == 0
+    lp = api.fit_scratch_bytes(1000, 4, grid, "bf16")
+    assert lp >= 4 * 1000 * 4
+    wd = api.fit_scratch_bytes(1000, 4, grid, "bf16", weight="wendland", h=0.05)
+    assert wd > lp + 2 * 4 * 1000 * 4
+
+
+def test_server_arguments_rejected_without_device(lib):
+    from paper_1408_0677_amd import _lib
+    out = ctypes.c_void_p()
+    assert lib.mls_server_create(0, 1 << 20, 0, 0, ctypes.byref(out)) == -1
+    assert b"slots" in lib.mls_server_last_error()
+    assert lib.mls_server_create(0, 1 << 20, 4, 1 << 20, ctypes.byref(out)) == -5
+    assert b"exceed the budget" in lib.mls_server_last_error()
+    assert lib.mls_server_create(0, 1 << 20, 1, 0, None) == -1
+    pid = ctypes.c_uint64()
+    assert lib.mls_server_put_points(None, None, None, 1, 1, ctypes.byref(pid)) == -1
+    req = _lib.MlsRequest()
+    t = ctypes.c_uint64()
+    assert lib.mls_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == -1
+    res = _lib.MlsResult()
+    assert lib.mls_server_poll(None, 1, ctypes.byref(res)) == -1
+    assert lib.mls_status_string(-5) == b"MLS_ERR_OVER_BUDGET"
+    assert lib.mls_status_string(1) == b"MLS_PENDING"

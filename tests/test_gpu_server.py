@@ -1,0 +1,143 @@
+"""GPU tests of the served form (mls_server_*): requests of uneven size and
+kind run concurrently on several slots; every result is bit-identical to
+the same fit run alone through mls_fit, and to the same request served on a
+one-slot server."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_requests(seed=0, count=12):
+    from paper_1408_0677_amd import workloads as wl
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for q in range(count):
+        n = int(rng.integers(200, 4000))
+        d = int(rng.integers(1, 20))
+        side = int(rng.integers(17, 200))
+        basis = ["constant", "linear", "quadratic"][q % 3]
+        prec = ["f64", "bf16", "fp16"][(q // 3) % 3]
+        weight = "wendland" if (q % 4 == 3 and prec != "f64") else "gaussian"
+        pts = wl.mixture_points(rng, n, k=3) if q % 2 else rng.random((n, 2))
+        vals = rng.standard_normal((n, d))
+        h = float(np.sqrt(30.0 / (np.pi * n))) * (2.0 if weight == "wendland" else 1.0)
+        reqs.append(dict(pts=pts.astype(np.float32), vals=vals.astype(np.float32),
+                         grid=wl.pixel_grid(side, side + q), basis=basis, precision=prec,
+                         weight=weight, h=h))
+    return reqs
+
+
+def test_served_equals_direct(torch_dev):
+    import torch
+    from paper_1408_0677_amd import api
+    reqs = make_requests()
+    note(f"case server mix of {len(reqs)} requests on 4 slots")
+    srv = api.Server(slots=4, hbm_budget=1 << 30, slot_scratch=64 << 20)
+    tickets, outs = [], []
+    for r in reqs:
+        P = torch.from_numpy(r["pts"]).cuda()
+        V = torch.from_numpy(r["vals"]).cuda()
+        pid = srv.put_points(P, V)
+        W, H = r["grid"]["width"], r["grid"]["height"]
+        out = torch.full((V.shape[1], H, W), -7.0, device="cuda")
+        deg = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+        t = srv.submit(pid, r["grid"], out, deg, basis=r["basis"], weight=r["weight"], h=r["h"],
+                       precision=r["precision"])
+        tickets.append(t)
+        outs.append((out, deg, P, V))
+    results = [srv.wait(t) for t in tickets]
+    for r, res, (out, deg, P, V) in zip(reqs, results, outs):
+        assert res["status"] == 0, res
+        assert res["t_submit"] <= res["t_admit"] <= res["t_start"] <= res["t_end"]
+        ref, rdeg = api.fit(P, V, r["grid"], basis=r["basis"], weight=r["weight"], h=r["h"],
+                            precision=r["precision"])
+        torch.cuda.synchronize()
+        assert torch.equal(deg, rdeg)
+        assert torch.equal(out.view(torch.int32), ref.view(torch.int32)), r["precision"]
+    srv.close()
+
+
+def test_alone_vs_mix(torch_dev):
+    """One request served alone on a one-slot server and inside a busy mix
+    on a four-slot server gives identical bits."""
+    import torch
+    from paper_1408_0677_amd import api
+    reqs = make_requests(seed=1, count=9)
+    probe = reqs[4]
+    note("case alone vs mix")
+
+    def serve(slots, with_mix):
+        srv = api.Server(slots=slots, hbm_budget=1 << 30, slot_scratch=64 << 20)
+        keep = []
+        todo = (reqs if with_mix else []) + [probe] + (reqs if with_mix else [])
+        probe_out = None
+        tickets = []
+        for r in todo:
+            P = torch.from_numpy(r["pts"]).cuda()
+            V = torch.from_numpy(r["vals"]).cuda()
+            pid = srv.put_points(P, V)
+            W, H = r["grid"]["width"], r["grid"]["height"]
+            out = torch.empty((V.shape[1], H, W), device="cuda")
+            t = srv.submit(pid, r["grid"], out, None, basis=r["basis"], weight=r["weight"],
+                           h=r["h"], precision=r["precision"])
+            tickets.append(t)
+            keep.append(out)
+            if r is probe and probe_out is None:
+                probe_out = out
+        for t in tickets:
+            assert srv.wait(t)["status"] == 0
+        srv.close()
+        return probe_out.cpu().numpy()
+
+    alone = serve(1, False)
+    mixed = serve(4, True)
+    assert np.array_equal(alone.view(np.uint32), mixed.view(np.uint32))
+
+
+def test_errors_are_isolated(torch_dev):
+    import torch
+    from paper_1408_0677_amd import api
+    note("case server errors")
+    srv = api.Server(slots=2, hbm_budget=256 << 20, slot_scratch=1 << 20)
+    P = torch.rand(500, 2, device="cuda")
+    V = torch.rand(500, 3, device="cuda")
+    pid = srv.put_points(P, V)
+    grid = {"x0": 0.0, "y0": 0.0, "dx": 0.02, "dy": 0.02, "width": 40, "height": 40}
+    out = torch.empty((3, 40, 40), device="cuda")
+    bad = srv.submit(pid, grid, out, weight="invpow")            # unsupported kind
+    good = srv.submit(pid, grid, torch.empty((3, 40, 40), device="cuda"), h=0.1)
+    rb = srv.wait(bad)
+    rg = srv.wait(good)
+    assert rb["status"] == -7 and "weight kind" in rb["detail"]
+    assert rg["status"] == 0
+    # a request whose staging scratch cannot fit a slot is refused at submit
+    big = torch.rand(200_000, 2, device="cuda")
+    bigv = torch.rand(200_000, 4, device="cuda")
+    pid2 = srv.put_points(big, bigv)
+    with pytest.raises(api.ServerError) as ei:
+        srv.submit(pid2, grid, torch.empty((4, 40, 40), device="cuda"), precision="bf16")
+    assert "OVER_BUDGET" in str(ei.value)
+    # a point set larger than the budget is refused
+    with pytest.raises(api.ServerError):
+        srv.put_points(torch.rand(30_000_000, 2, device="cuda"),
+                       torch.rand(30_000_000, 1, device="cuda"))
+    srv.release_points(pid)
+    with pytest.raises(api.ServerError):
+        srv.submit(pid, grid, out)
+    srv.close()
