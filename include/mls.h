@@ -122,6 +122,12 @@ typedef struct mls_context mls_context;
 #define MLS_MAX_D_LP 1024
 /* Largest point count. */
 #define MLS_MAX_N ((int64_t)1 << 31)
+/* 16-bit precisions: largest span of a 16 x 16 node tile, 15 max(|dx|, |dy|)
+ * / h, per basis (the constant basis has no limit).  The tile shares one
+ * moment frame; moving the float32 moments to a node that far from it
+ * cancels digits (the quadratic basis more, through fourth powers). */
+#define MLS_LP_MAX_TILE_SPAN_LINEAR 4.0
+#define MLS_LP_MAX_TILE_SPAN_QUADRATIC 2.5
 
 /* Status name ("MLS_OK", ...); never NULL. */
 const char* mls_status_string(mls_status s);
@@ -153,10 +159,15 @@ void mls_context_destroy(mls_context* ctx);
  *  d_degree  uint8 [height][width] output (accepted degree, 255 for
  *            undetermined), device, or NULL
  * Supported in this build: the Gaussian weight with all three bases and all
- * precisions; other combinations return MLS_ERR_UNSUPPORTED.  MLS_PREC_FP16
- * also returns MLS_ERR_UNSUPPORTED when the grid spacing is so coarse
- * against h that tile-frame features would leave the float16 range.
- * The 16-bit precisions use library scratch of about 4 n d bytes.
+ * precisions, the Wendland C2 weight with the 16-bit precisions (through a
+ * device cell list); other combinations (the inverse-power weight, Wendland
+ * with MLS_PREC_F64) return MLS_ERR_UNSUPPORTED.  The 16-bit precisions
+ * also return MLS_ERR_UNSUPPORTED when a node tile spans more than
+ * MLS_LP_MAX_TILE_SPAN_<basis> (linear, quadratic), and MLS_PREC_FP16 when
+ * tile-frame features would leave the float16 range; MLS_PREC_F64 serves
+ * such coarse grids.
+ * The 16-bit precisions use library scratch of about 4 n d bytes (plus the
+ * cell list for Wendland); mls_fit_scratch_bytes gives the exact figure.
  */
 mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
                    int64_t n, int32_t d, int32_t basis, const mls_weight* weight,

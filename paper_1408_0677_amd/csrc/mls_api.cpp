@@ -301,6 +301,18 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
     return MLS_OK;
   }
   const bool fp16 = precision == MLS_PREC_FP16;
+  // The 16-bit contraction accumulates moments in a frame shared by a
+  // 16 x 16 node tile; moving them to a node far from the frame's origin
+  // cancels digits the float32 accumulator cannot spare (the constant basis
+  // has no frame-dependent moments).  Grids that coarse against h are small:
+  // the float64 path serves them.
+  const double extent = mls::lp_tile_extent(grid->dx, grid->dy, weight->h);
+  const double span_max = basis == MLS_BASIS_QUADRATIC ? MLS_LP_MAX_TILE_SPAN_QUADRATIC
+                          : basis == MLS_BASIS_LINEAR  ? MLS_LP_MAX_TILE_SPAN_LINEAR
+                                                       : HUGE_VAL;
+  if (extent > span_max)
+    return fail(MLS_ERR_UNSUPPORTED, "a 16 x 16 node tile spans %.2f h (> %.1f h for this "
+                "basis); use MLS_PREC_F64 for grids this coarse against h", extent, span_max);
   if (fp16) {
     // tile-frame features reach |u| <= 8 + half the tile diagonal (in h);
     // the largest, u^4 times an attribute in [-1, 1], must stay finite

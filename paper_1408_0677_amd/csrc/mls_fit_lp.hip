@@ -8,25 +8,35 @@
 // the quadratic basis.  So
 //   - every feature g (moment monomial or basis x attribute) is carried as
 //     an S-term expansion g = g_1 + ... + g_S of 16-bit numbers (each term
-//     the rounding of what the previous terms left), and the contraction
-//     issues one MFMA per term into the same float32 accumulator: the
-//     products are exact, the accumulator holds about 24 bits;
-//   - the weight w(node, point) is rounded once and the same rounded weight
-//     multiplies every feature of that pair, so the result is the exact MLS
-//     fit for slightly perturbed weights (MLS reproduces its basis for any
-//     positive weights);
+//     the rounding of what the previous terms left);
+//   - the weight is carried as w_hi + w_lo (two terms) when S >= 2;
+//   - the contraction issues, per feature tile, w_hi x g_s for every term
+//     plus w_lo x g_1, all into one float32 accumulator: the products are
+//     exact and each weight x feature product keeps far more bits than the
+//     float32 accumulator;
+//   - the same weight multiplies every feature of a (node, point) pair, so
+//     rounding it only perturbs the weight function;
 //   - attributes are staged in [-1, 1] (mls_stage.hip) and mapped back.
 //
-// Work split.  A workgroup (4 waves) owns a 16 x 16 node tile and one slab
-// of attributes: the slab's features are the moment monomials plus
+// Work split.  A workgroup owns a 16 x 16 node tile and one slab of
+// attributes: the slab's features are the moment monomials plus
 // basis x attribute products for its D_s attributes, at most 16 NTS
-// columns, so the per-node accumulators fit in registers (each wave: 4 row
-// strips x NTS feature tiles of 16 x 16 float32).  Every slab repeats the
-// moments, which lets each slab solve its own nodes.  Points stream through
-// double-buffered LDS in chunks of 32 (one MFMA k-step): Gaussian factors
-// gx[col][k], gy[row][k] in float32, and the feature terms
-// G[s][j][k] in 16 bits; while the MFMAs of one chunk run the workgroup
-// fills the next chunk into the other buffer.
+// columns, so the per-node accumulators fit in registers.  Every slab
+// repeats the moments, which lets each slab solve its own nodes.
+// Eight waves: waves 0-3 issue the matrix instructions (each owns 4 row
+// strips x NTS feature tiles of 16 x 16 float32), waves 4-7 produce.  Points
+// stream in chunks of 64 through a three-stage pipeline, one barrier per
+// chunk:
+//   producers, iteration c:  load the raw chunk c + 2 (coordinates, staged
+//                            attributes) from global memory into registers;
+//                            turn raw chunk c + 1 (in LDS) into weight
+//                            tables and 16-bit feature terms; store raw
+//                            chunk c + 2 to LDS
+//   MFMA waves, iteration c: build the A operands (weights) from the tables
+//                            of chunk c and run its MFMAs
+// so the global-memory latency of a chunk is hidden behind a whole chunk of
+// matrix work.  With the Wendland weight the chunks walk the runs of
+// cell-sorted points that the tile's support can reach (mls_cells.hip).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -41,19 +51,31 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-constexpr int kThreads = 256;
-constexpr int kWaves = 4;
+constexpr int kMmaWaves = 4;
+constexpr int kProd = 256;                 // producer threads
+constexpr int kThreads = kMmaWaves * 64 + kProd;
 constexpr int kCols = 16;
-constexpr int R = 4;                  // row strips per wave
-constexpr int kRows = kWaves * R;     // 16
-constexpr int KT = 32;                // points per chunk (one MFMA k-step)
-constexpr int KSF = KT + 4;           // float32 table stride (floats)
-constexpr int KSH = KT + 8;           // 16-bit feature stride (elements; 80 B rows)
-constexpr int kEpiWaves = 2;
+constexpr int R = 4;                       // row strips per MFMA wave
+constexpr int kRows = kMmaWaves * R;       // 16
+constexpr int KT = 64;                     // points per chunk (two MFMA k-steps)
+constexpr int KSF = KT + 4;                // float32 table stride (floats)
+constexpr int KSH = KT + 8;                // 16-bit feature stride (elements, 144 B)
+constexpr int kDsCap = 40;                 // attributes per slab at most
 
 template <typename T> struct Vec8;
 template <> struct Vec8<__bf16> { typedef bf16x8 type; };
 template <> struct Vec8<_Float16> { typedef halfx8 type; };
+
+// Common factor applied to every weight before it is rounded to the 16-bit
+// operand.  float16 has a 5-bit exponent: a Gaussian weight below 6e-5
+// (r > 3.1 h) would land among its subnormals and lose most of its digits,
+// so the fp16 path works with weights times 2^15 (largest 32768, still
+// below the format's 65504; weights of r < 5.2 h stay normal).  bfloat16
+// shares float32's exponent range and needs no factor.  The solve divides
+// the weight sum by the factor before the floor test; the pivots are
+// equilibrated and do not see it.
+template <typename T> struct WeightGain { static constexpr float value = 1.0f; };
+template <> struct WeightGain<_Float16> { static constexpr float value = 32768.0f; };
 
 __device__ __forceinline__ floatx4 mfma16(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -63,109 +85,134 @@ __device__ __forceinline__ floatx4 mfma16(halfx8 a, halfx8 b, floatx4 c) {
 }
 
 struct LPParams {
-  const float* pts;       // [n][2]
+  const float* pts;       // [n][2] (cell order for the Wendland weight)
   const float* vals_t;    // [D][n] staged attributes in [-1, 1]
   const float* shift;     // [D]
   const float* scale;     // [D]
   int64_t n;
-  int D, Ds, nslab, F;    // F = features of a full slab
+  int D, Ds, nslab;
   float inv_h;
   double inv_hd;
   double x0, y0, dx, dy;
   int W, H, tiles_x, tiles;
   double tau, floor_w;
-  float cutoff2;          // points whose u^2 exceeds this for every node get no weight
+  float cutoff2;          // points with u^2 beyond this get no features
   float* fields;
   uint8_t* deg_out;
-  // compact support: points (and vals_t) in cell order, cell offsets, tiles
-  // in the order to run them
   const uint32_t* cell_start;
   const uint32_t* torder;
   int ncx, ncy;
   CellGeom geom;
 };
 
-// Chunks of at most KT consecutive points: all points (dense), or the runs
-// of cells that a tile's support can reach, one cell row at a time.
-struct ChunkCursor {
-  int64_t k, kend;   // current chunk starts at k; its run ends at kend
-  int cy, cy1;       // cell row of the run, last cell row
+// A chunk: points [k, k + kn).  Chunks never straddle two cell rows.
+struct Chunk {
+  int64_t k;
+  int kn;
+  bool valid;
+};
+
+// Walks the chunks of a tile: all points (dense), or the runs of cells in
+// rows cy0..cy1, columns cx0..cx1 (each run contiguous in cell order).
+struct Walker {
+  int64_t k, kend;
+  int cy, cy1, cx0, cx1;
   bool done;
 };
 
 template <bool CELLS>
-__device__ __forceinline__ void cursor_row(const LPParams& p, ChunkCursor& cu, int cx0, int cx1) {
-  // advance to the next non-empty run at or after row cu.cy
-  while (cu.cy <= cu.cy1) {
-    const int64_t a = p.cell_start[cu.cy * p.ncx + cx0];
-    const int64_t b = p.cell_start[cu.cy * p.ncx + cx1 + 1];
+__device__ __forceinline__ void walker_row(const LPParams& p, Walker& w) {
+  while (w.cy <= w.cy1) {
+    const int64_t a = p.cell_start[w.cy * p.ncx + w.cx0];
+    const int64_t b = p.cell_start[w.cy * p.ncx + w.cx1 + 1];
     if (b > a) {
-      cu.k = a;
-      cu.kend = b;
+      w.k = a;
+      w.kend = b;
       return;
     }
-    ++cu.cy;
+    ++w.cy;
   }
-  cu.done = true;
+  w.done = true;
 }
 
 template <bool CELLS>
-__device__ __forceinline__ ChunkCursor cursor_begin(const LPParams& p, int cx0, int cx1, int cy0,
-                                                    int cy1) {
-  ChunkCursor cu;
-  cu.done = false;
+__device__ __forceinline__ Walker walker_begin(const LPParams& p, int cx0, int cx1, int cy0,
+                                               int cy1) {
+  Walker w;
+  w.done = false;
+  w.cx0 = cx0;
+  w.cx1 = cx1;
   if (!CELLS) {
-    cu.k = 0;
-    cu.kend = p.n;
-    cu.cy = 0;
-    cu.cy1 = 0;
-    return cu;
+    w.k = 0;
+    w.kend = p.n;
+    w.cy = w.cy1 = 0;
+    return w;
   }
-  cu.cy = cy0;
-  cu.cy1 = cy1;
-  cursor_row<CELLS>(p, cu, cx0, cx1);
-  return cu;
+  w.cy = cy0;
+  w.cy1 = cy1;
+  walker_row<CELLS>(p, w);
+  return w;
 }
 
+// Take the next chunk (invalid once the walk is over).
 template <bool CELLS>
-__device__ __forceinline__ void cursor_next(const LPParams& p, ChunkCursor& cu, int cx0, int cx1) {
-  cu.k += KT;
-  if (cu.k < cu.kend) return;
-  if (!CELLS) {
-    cu.done = true;
-    return;
+__device__ __forceinline__ Chunk walker_take(const LPParams& p, Walker& w) {
+  Chunk c;
+  c.valid = !w.done;
+  c.k = w.k;
+  c.kn = 0;
+  if (w.done) return c;
+  const int64_t left = w.kend - w.k;
+  c.kn = left < KT ? (int)left : KT;
+  w.k += c.kn;
+  if (w.k >= w.kend) {
+    if (!CELLS) {
+      w.done = true;
+    } else {
+      ++w.cy;
+      walker_row<CELLS>(p, w);
+    }
   }
-  ++cu.cy;
-  cursor_row<CELLS>(p, cu, cx0, cx1);
+  return c;
 }
 
 template <int DEG, int NTS, int S, typename T>
 struct LPLayout {
+  static constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
+  static constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
   static constexpr int kFP = NTS * 16;
-  static constexpr int kGxB = 0;                                   // [16][KSF] float
-  static constexpr int kGyB = kGxB + kCols * KSF * 4;              // [16][KSF] float
-  static constexpr int kGB = kGyB + kRows * KSF * 4;               // [S][kFP][KSH] T
-  static constexpr int kBuf = kGB + S * kFP * KSH * 2;             // bytes, one buffer
-  static constexpr int kEpiStride = kFP + 1;                       // floats
-  static constexpr int kEpi = kEpiWaves * 16 * R * kEpiStride * 4;  // bytes
-  static constexpr int kBytes = 2 * kBuf > kEpi ? 2 * kBuf : kEpi;
+  static constexpr int kDsFit = (kFP - nmom) / m > 0 ? (kFP - nmom) / m : 0;
+  static constexpr int kDsMax = kDsFit < kDsCap ? kDsFit : kDsCap;
+  // raw chunk: x[KT], y[KT], v[kDsMax][KT]
+  static constexpr int kRawFloats = (2 + kDsMax) * KT;
+  static constexpr int kRawIt = (kRawFloats + kProd - 1) / kProd;
+  static constexpr int kFeatB = S * kFP * KSH * 2;            // one feature buffer
+  static constexpr int kTabB = (kCols + kRows) * KSF * 4;     // one weight table
+  static constexpr int kRawB = kRawFloats * 4;
+  static constexpr int kFeat0 = 0;
+  static constexpr int kTab0 = kFeat0 + 2 * kFeatB;
+  static constexpr int kRaw0 = kTab0 + 2 * kTabB;
+  static constexpr int kLoop = kRaw0 + 2 * kRawB;
+  static constexpr int kEpiStride = kFP + 1;                  // floats
+  static constexpr int kEpi = kMmaWaves * 16 * R * kEpiStride * 4;
+  static constexpr int kBytes = kLoop > kEpi ? kLoop : kEpi;
+  static_assert(kBytes <= 160 * 1024, "LDS budget");
 };
 
-// Split v into S 16-bit terms (each the rounding of the remainder).
-template <int S, typename T>
-__device__ __forceinline__ void split_terms(float v, T* out) {
-  float r = v;
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const T t = (T)r;
-    out[s] = t;
-    r = r - (float)t;
-  }
+// Exponents of the moment monomials (ordered by total degree, then by the
+// power of u_y): entry j is u_x^kMonoA[j] u_y^kMonoB[j].
+__constant__ int8_t kMonoA[15] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
+__constant__ int8_t kMonoB[15] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
+// basis term j of [1, ux, uy, ux^2, ux uy, uy^2]
+__constant__ int8_t kBasA[6] = {0, 1, 0, 2, 1, 0};
+__constant__ int8_t kBasB[6] = {0, 0, 1, 0, 1, 2};
+
+__device__ __forceinline__ float ipow(float x, int e) {
+  float r = 1.0f;
+  for (int q = 0; q < e; ++q) r *= x;
+  return r;
 }
 
-// Fill one chunk buffer: Gaussian factors and the slab's feature terms for
-// points [k0, k0 + KT).  Points past n, and points farther than the cutoff
-// from every node of the tile, get zero weight and zero features.
 // Offset of node column c0 + col (row r0 + row) from the tile anchor, in
 // units of h, computed in float64 from the grid definition.
 __device__ __forceinline__ double node_offset_xd(const LPParams& p, int c0, int col, float cxr) {
@@ -174,112 +221,8 @@ __device__ __forceinline__ double node_offset_xd(const LPParams& p, int c0, int 
 __device__ __forceinline__ double node_offset_yd(const LPParams& p, int r0, int row, float cyr) {
   return (p.y0 + (double)(r0 + row) * p.dy - (double)cyr) * p.inv_hd;
 }
-__device__ __forceinline__ float node_offset_x(const LPParams& p, int c0, int col, float cxr) {
-  return (float)node_offset_xd(p, c0, col, cxr);
-}
-__device__ __forceinline__ float node_offset_y(const LPParams& p, int r0, int row, float cyr) {
-  return (float)node_offset_yd(p, r0, row, cyr);
-}
 
-template <int DEG, int NTS, int S, typename T, bool WEND>
-__device__ __forceinline__ void stage_chunk(const LPParams& p, char* buf, int64_t k0, int64_t kend,
-                                            int slab, int tid, int c0, int r0, float cxr,
-                                            float cyr) {
-  using L = LPLayout<DEG, NTS, S, T>;
-  constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
-  constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
-  float* gx = (float*)(buf + L::kGxB);
-  float* gy = (float*)(buf + L::kGyB);
-  T* G = (T*)(buf + L::kGB);
-  // Gaussian factors: 32 rows (16 columns, 16 rows) x 32 points = 4 per thread
-#pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int e = tid + it * kThreads;
-    const int k = e & (KT - 1), row = e >> 5;
-    const int64_t gi = k0 + k;
-    // Gaussian: the separable factor exp(-u^2); Wendland: u^2, combined per
-    // pair when the A operand is built.  Points past the run: Gaussian 0,
-    // Wendland a distance beyond the support.
-    float v = WEND ? 4.0f : 0.0f;
-    if (gi < kend) {
-      float u;
-      if (row < kCols) u = (p.pts[2 * gi] - cxr) * p.inv_h - node_offset_x(p, c0, row, cxr);
-      else u = (p.pts[2 * gi + 1] - cyr) * p.inv_h - node_offset_y(p, r0, row - kCols, cyr);
-      v = WEND ? u * u : __expf(-u * u);
-    }
-    if (row < kCols) gx[row * KSF + k] = v;
-    else gy[(row - kCols) * KSF + k] = v;
-  }
-  // features: items (feature j, point pair) -> S packed 32-bit writes
-  const int d0 = slab * p.Ds;
-  const int Ds = min(p.Ds, p.D - d0);
-  const int F = nmom + m * Ds;
-  for (int e = tid; e < L::kFP * (KT / 2); e += kThreads) {
-    const int kp = (e & (KT / 2 - 1)) * 2, j = e / (KT / 2);
-    float v[2] = {0.0f, 0.0f};
-#pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-      const int64_t gi = k0 + kp + h2;
-      if (gi < kend && j < F) {
-        const float ux = (p.pts[2 * gi] - cxr) * p.inv_h;
-        const float uy = (p.pts[2 * gi + 1] - cyr) * p.inv_h;
-        if (ux * ux + uy * uy <= p.cutoff2) {
-          if (j < nmom) {
-            int t = 0;
-            while ((t + 1) * (t + 2) / 2 <= j) ++t;
-            const int b = j - t * (t + 1) / 2, a = t - b;
-            float w = 1.0f;
-            for (int q = 0; q < a; ++q) w *= ux;
-            for (int q = 0; q < b; ++q) w *= uy;
-            v[h2] = w;
-          } else {
-            const int jj = j - nmom;
-            const int bj = jj / Ds, d = jj - bj * Ds;
-            const float f = p.vals_t[(int64_t)(d0 + d) * p.n + gi];
-            float bv = 1.0f;
-            if (bj == 1) bv = ux;
-            else if (bj == 2) bv = uy;
-            else if (bj == 3) bv = ux * ux;
-            else if (bj == 4) bv = ux * uy;
-            else if (bj == 5) bv = uy * uy;
-            v[h2] = bv * f;
-          }
-        }
-      }
-    }
-    T t0[S], t1[S];
-    split_terms<S, T>(v[0], t0);
-    split_terms<S, T>(v[1], t1);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      T* dst = G + ((size_t)s * L::kFP + j) * KSH + kp;
-      dst[0] = t0[s];
-      dst[1] = t1[s];
-    }
-  }
-}
-
-template <int DEG, int R_, typename Acc>
-__device__ void solve_tile_nodes_lp(const LPParams& p, const Acc* epi, int stride, int lane,
-                                    int wave, int r0, int c0, int slab, int64_t plane,
-                                    float cxr, float cyr) {
-  const int d0 = slab * p.Ds;
-  const int Ds = min(p.Ds, p.D - d0);
-  for (int node = lane; node < 16 * R_; node += 64) {
-    const int t = node / 16, col = node % 16;
-    const int r = r0 + wave * R_ + t, c = c0 + col;
-    if (r >= p.H || c >= p.W) continue;
-    const double ex = node_offset_xd(p, c0, col, cxr);
-    const double ey = node_offset_yd(p, r0, wave * R_ + t, cyr);
-    const int64_t off = (int64_t)r * p.W + c;
-    uint8_t code = solve_node<DEG, Acc>(epi + node * stride, Ds, ex, ey, p.tau, p.floor_w,
-                                        p.fields + (int64_t)d0 * plane + off, plane,
-                                        p.shift + d0, p.scale + d0);
-    if (p.deg_out && slab == 0) p.deg_out[off] = code;
-  }
-}
-
-// Wendland C2 weight (1 - s)^4 (4 s + 1) for s = r / h < 1.
+// Wendland C2 weight (1 - s)^4 (4 s + 1) for s = r / h < 1, from s^2.
 __device__ __forceinline__ float wendland_c2(float s2) {
   const float s = __builtin_sqrtf(s2);
   const float t = 1.0f - s;
@@ -287,24 +230,146 @@ __device__ __forceinline__ float wendland_c2(float s2) {
   return s < 1.0f ? t2 * t2 * (4.0f * s + 1.0f) : 0.0f;
 }
 
+// Producer: global -> registers for one raw chunk.
+template <int DEG, int NTS, int S, typename T>
+__device__ __forceinline__ void raw_load(const LPParams& p, const Chunk& ch, int d0, int Ds,
+                                         int pt, float (&r)[LPLayout<DEG, NTS, S, T>::kRawIt]) {
+  using L = LPLayout<DEG, NTS, S, T>;
+#pragma unroll
+  for (int it = 0; it < L::kRawIt; ++it) {
+    const int e = pt + it * kProd;
+    float v = 0.0f;
+    if (ch.valid && e < (2 + Ds) * KT) {
+      const int row = e / KT, k = e - row * KT;
+      if (k < ch.kn) {
+        const int64_t gi = ch.k + k;
+        if (row == 0) v = p.pts[2 * gi];
+        else if (row == 1) v = p.pts[2 * gi + 1];
+        else v = p.vals_t[(int64_t)(d0 + row - 2) * p.n + gi];
+      }
+    }
+    r[it] = v;
+  }
+}
+
+template <int DEG, int NTS, int S, typename T>
+__device__ __forceinline__ void raw_store(float* raw, int Ds, int pt,
+                                          const float (&r)[LPLayout<DEG, NTS, S, T>::kRawIt]) {
+  using L = LPLayout<DEG, NTS, S, T>;
+#pragma unroll
+  for (int it = 0; it < L::kRawIt; ++it) {
+    const int e = pt + it * kProd;
+    if (e < (2 + Ds) * KT) raw[e] = r[it];
+  }
+}
+
+// Producer: raw chunk (LDS) -> weight tables and feature terms (LDS).
+template <int DEG, int NTS, int S, typename T, bool WEND>
+__device__ __forceinline__ void make_chunk(const LPParams& p, const float* raw, int kn, int Ds,
+                                           float* tab, T* G, int pt, int c0, int r0, float cxr,
+                                           float cyr) {
+  using L = LPLayout<DEG, NTS, S, T>;
+  constexpr int m = L::m, nmom = L::nmom;
+  const float* rx = raw;
+  const float* ry = raw + KT;
+  const float* rv = raw + 2 * KT;
+  // weight tables: 32 rows (16 node columns, 16 node rows) x 64 points.
+  // Gaussian: the separable factor exp(-u^2); Wendland: u^2 (combined per
+  // pair when the A operand is built).  Points past the chunk: Gaussian 0,
+  // Wendland a distance beyond the support.
+#pragma unroll
+  for (int it = 0; it < (kCols + kRows) * KT / kProd; ++it) {
+    const int e = pt + it * kProd;
+    const int k = e & (KT - 1), row = e / KT;
+    float v = WEND ? 4.0f : 0.0f;
+    if (k < kn) {
+      float u;
+      if (row < kCols) u = (rx[k] - cxr) * p.inv_h - (float)node_offset_xd(p, c0, row, cxr);
+      else u = (ry[k] - cyr) * p.inv_h - (float)node_offset_yd(p, r0, row - kCols, cyr);
+      // the factor rides on the column table (the weight is gx * gy)
+      v = WEND ? u * u : __expf(-u * u) * (row < kCols ? WeightGain<T>::value : 1.0f);
+    }
+    tab[row * KSF + k] = v;
+  }
+  // features: items (feature j, point pair); S packed 32-bit writes each
+  const int F = nmom + m * Ds;
+  for (int e = pt; e < L::kFP * (KT / 2); e += kProd) {
+    const int kp = (e & (KT / 2 - 1)) * 2, j = e / (KT / 2);
+    float v[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int k = kp + h2;
+      if (k < kn && j < F) {
+        const float ux = (rx[k] - cxr) * p.inv_h;
+        const float uy = (ry[k] - cyr) * p.inv_h;
+        if (ux * ux + uy * uy <= p.cutoff2) {
+          if (j < nmom) {
+            v[h2] = ipow(ux, kMonoA[j]) * ipow(uy, kMonoB[j]);
+          } else {
+            const int jj = j - nmom;
+            const int bj = jj / Ds, d = jj - bj * Ds;
+            v[h2] = ipow(ux, kBasA[bj]) * ipow(uy, kBasB[bj]) * rv[d * KT + k];
+          }
+        }
+      }
+    }
+    float r0v = v[0], r1v = v[1];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const T t0 = (T)r0v, t1 = (T)r1v;
+      r0v -= (float)t0;
+      r1v -= (float)t1;
+      T* dst = G + ((size_t)s * L::kFP + j) * KSH + kp;
+      dst[0] = t0;
+      dst[1] = t1;
+    }
+  }
+}
+
 template <int DEG, int NTS, int S, typename T, bool WEND, bool CELLS>
-__global__ __launch_bounds__(kThreads, 2) void fit_lp_kernel(LPParams p) {
+__global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   using L = LPLayout<DEG, NTS, S, T>;
   typedef typename Vec8<T>::type vec8;
   extern __shared__ __attribute__((aligned(16))) char lds_lp[];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool mma = wave < kMmaWaves;
+  const int pt = tid - kMmaWaves * 64;   // producer thread index
   const int slab = blockIdx.x / p.tiles;
   const int tile = CELLS ? (int)p.torder[blockIdx.x % p.tiles] : (int)(blockIdx.x % p.tiles);
   const int c0 = (tile % p.tiles_x) * kCols;
   const int r0 = (tile / p.tiles_x) * kRows;
-  // tile anchor (rounded to float32: the frame only has to be close to the
-  // tile, the offsets below are taken in the same float32 frame)
+  const int d0 = slab * p.Ds;
+  const int Ds = min(p.Ds, p.D - d0);
+  // tile anchor (rounded to float32; node offsets are taken in this frame)
   const float cxr = (float)(p.x0 + (double)(c0 + kCols / 2) * p.dx);
   const float cyr = (float)(p.y0 + (double)(r0 + kRows / 2) * p.dy);
   int cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
-  if (CELLS) tile_cell_range(p.geom, tile % p.tiles_x, tile / p.tiles_x, p.ncx, p.ncy, &cx0, &cx1,
-                             &cy0, &cy1);
+  if (CELLS)
+    tile_cell_range(p.geom, tile % p.tiles_x, tile / p.tiles_x, p.ncx, p.ncy, &cx0, &cx1, &cy0,
+                    &cy1);
+
+  // double buffers, selected by chunk parity b
+  auto feat = [&](int b) { return (T*)(lds_lp + L::kFeat0 + b * L::kFeatB); };
+  auto tab = [&](int b) { return (float*)(lds_lp + L::kTab0 + b * L::kTabB); };
+  auto raw = [&](int b) { return (float*)(lds_lp + L::kRaw0 + b * L::kRawB); };
+
+  Walker wk = walker_begin<CELLS>(p, cx0, cx1, cy0, cy1);
+  Chunk ch0 = walker_take<CELLS>(p, wk);
+  Chunk ch1 = walker_take<CELLS>(p, wk);
+
+  // prologue: raw 0 and 1 to LDS, then chunk 0's tables and features
+  float rr[L::kRawIt];
+  if (!mma) {
+    raw_load<DEG, NTS, S, T>(p, ch0, d0, Ds, pt, rr);
+    raw_store<DEG, NTS, S, T>(raw(0), Ds, pt, rr);
+    raw_load<DEG, NTS, S, T>(p, ch1, d0, Ds, pt, rr);
+    raw_store<DEG, NTS, S, T>(raw(1), Ds, pt, rr);
+  }
+  __syncthreads();
+  if (!mma && ch0.valid)
+    make_chunk<DEG, NTS, S, T, WEND>(p, raw(0), ch0.kn, Ds, tab(0), feat(0), pt, c0, r0, cxr, cyr);
+  __syncthreads();
 
   floatx4 acc[R][NTS];
 #pragma unroll
@@ -312,73 +377,93 @@ __global__ __launch_bounds__(kThreads, 2) void fit_lp_kernel(LPParams p) {
 #pragma unroll
     for (int q = 0; q < NTS; ++q) acc[t][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  ChunkCursor cu = cursor_begin<CELLS>(p, cx0, cx1, cy0, cy1);
-  if (!cu.done)
-    stage_chunk<DEG, NTS, S, T, WEND>(p, lds_lp, cu.k, cu.kend, slab, tid, c0, r0, cxr, cyr);
-  __syncthreads();
-
   const int i = lane & 15;
-  const int k8 = (lane >> 4) * 8;   // this lane's 8 points of the 32
+  const int k8 = (lane >> 4) * 8;   // this lane's 8 points of a 32-point k-step
   int c = 0;
-  while (!cu.done) {
-    const char* cur = lds_lp + (c & 1) * L::kBuf;
-    char* nxt = lds_lp + ((c & 1) ^ 1) * L::kBuf;
-    const float* gx = (const float*)(cur + L::kGxB);
-    const float* gy = (const float*)(cur + L::kGyB);
-    const T* G = (const T*)(cur + L::kGB);
-    // A operands: weights of the wave's 4 row strips x the lane's 8 points
-    float wx[8];
+  while (ch0.valid) {
+    const Chunk ch2 = walker_take<CELLS>(p, wk);
+    if (mma) {
+      const float* gx = tab(c & 1);
+      const float* gy = tab(c & 1) + kCols * KSF;
+      const T* G = feat(c & 1);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) wx[q] = gx[i * KSF + k8 + q];
-    vec8 a[R];
+      for (int ks = 0; ks < KT; ks += 32) {
+        float wx[8];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const float* gyr = gy + (wave * R + t) * KSF + k8;
+        for (int q = 0; q < 8; ++q) wx[q] = gx[i * KSF + ks + k8 + q];
+        vec8 ahi[R], alo[R];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        a[t][q] = (T)(WEND ? wendland_c2(wx[q] + gyr[q]) : wx[q] * gyr[q]);
-    }
+        for (int t = 0; t < R; ++t) {
+          const float* gyr = gy + (wave * R + t) * KSF + ks + k8;
 #pragma unroll
-    for (int q = 0; q < NTS; ++q) {
+          for (int q = 0; q < 8; ++q) {
+            const float w =
+                WEND ? wendland_c2(wx[q] + gyr[q]) * WeightGain<T>::value : wx[q] * gyr[q];
+            const T hw = (T)w;
+            ahi[t][q] = hw;
+            alo[t][q] = (T)(w - (float)hw);
+          }
+        }
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const vec8 b = *(const vec8*)(G + ((size_t)s * L::kFP + q * 16 + i) * KSH + k8);
+        for (int q = 0; q < NTS; ++q) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) acc[t][q] = mfma16(a[t], b, acc[t][q]);
+          for (int s = 0; s < S; ++s) {
+            const vec8 b = *(const vec8*)(G + ((size_t)s * L::kFP + q * 16 + i) * KSH + ks + k8);
+#pragma unroll
+            for (int t = 0; t < R; ++t) acc[t][q] = mfma16(ahi[t], b, acc[t][q]);
+            if (S >= 2 && s == 0) {
+#pragma unroll
+              for (int t = 0; t < R; ++t) acc[t][q] = mfma16(alo[t], b, acc[t][q]);
+            }
+          }
+        }
       }
+    } else {
+      raw_load<DEG, NTS, S, T>(p, ch2, d0, Ds, pt, rr);      // chunk c + 2, in flight
+      if (ch1.valid)
+        make_chunk<DEG, NTS, S, T, WEND>(p, raw((c + 1) & 1), ch1.kn, Ds, tab((c + 1) & 1),
+                                         feat((c + 1) & 1), pt, c0, r0, cxr, cyr);
+      raw_store<DEG, NTS, S, T>(raw(c & 1), Ds, pt, rr);
     }
-    cursor_next<CELLS>(p, cu, cx0, cx1);
-    if (!cu.done)
-      stage_chunk<DEG, NTS, S, T, WEND>(p, nxt, cu.k, cu.kend, slab, tid, c0, r0, cxr, cyr);
     __syncthreads();
+    ch0 = ch1;
+    ch1 = ch2;
     ++c;
   }
 
-  // Epilogue: accumulators -> LDS [node][feature] (float32) -> solve.
-  const int64_t plane = (int64_t)p.W * p.H;
-  float* epi_all = (float*)lds_lp;
-#pragma unroll 1
-  for (int g = 0; g < kWaves; g += kEpiWaves) {
-    const bool mine = wave >= g && wave < g + kEpiWaves;
-    float* epi = epi_all + (wave - g) * 16 * R * L::kEpiStride;
-    if (mine) {
+  // Epilogue: accumulators -> LDS [wave][node][feature] (float32) -> solve.
+  float* epi = (float*)lds_lp;
+  if (mma) {
+    float* e = epi + wave * 16 * R * L::kEpiStride;
 #pragma unroll
-      for (int t = 0; t < R; ++t)
+    for (int t = 0; t < R; ++t)
 #pragma unroll
-        for (int q = 0; q < NTS; ++q)
+      for (int q = 0; q < NTS; ++q)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            // f32 16x16 MFMA result: lane holds row 4 (lane/16) + r, column lane%16
-            const int node = t * 16 + 4 * (lane >> 4) + r;
-            const int feat = q * 16 + (lane & 15);
-            epi[node * L::kEpiStride + feat] = acc[t][q][r];
-          }
+        for (int r = 0; r < 4; ++r) {
+          // f32 16x16 MFMA result: lane holds row 4 (lane/16) + r, column lane%16
+          const int node = t * 16 + 4 * (lane >> 4) + r;
+          const int feat_i = q * 16 + (lane & 15);
+          e[node * L::kEpiStride + feat_i] = acc[t][q][r];
+        }
+  }
+  __syncthreads();
+  if (mma) {
+    const float* e = epi + wave * 16 * R * L::kEpiStride;
+    const int64_t plane = (int64_t)p.W * p.H;
+    for (int node = lane; node < 16 * R; node += 64) {
+      const int t = node / 16, col = node % 16;
+      const int r = r0 + wave * R + t, cc = c0 + col;
+      if (r >= p.H || cc >= p.W) continue;
+      const double ex = node_offset_xd(p, c0, col, cxr);
+      const double ey = node_offset_yd(p, r0, wave * R + t, cyr);
+      const int64_t off = (int64_t)r * p.W + cc;
+      uint8_t code = solve_node<DEG, float>(e + node * L::kEpiStride, Ds, ex, ey, p.tau,
+                                            p.floor_w, p.fields + (int64_t)d0 * plane + off,
+                                            plane, p.shift + d0, p.scale + d0,
+                                            (double)WeightGain<T>::value);
+      if (p.deg_out && slab == 0) p.deg_out[off] = code;
     }
-    __syncthreads();
-    if (mine)
-      solve_tile_nodes_lp<DEG, R, float>(p, epi, L::kEpiStride, lane, wave, r0, c0, slab, plane,
-                                         cxr, cyr);
-    __syncthreads();
   }
 }
 
@@ -435,13 +520,14 @@ hipError_t launch_lp_terms(const LPParams& p, int deg, int nts, int terms, hipSt
 
 }  // namespace
 
-// Slab plan: feature tiles per slab (1..8) and attributes per slab that cover
-// D with the fewest padded columns in total.
+// Slab plan: feature tiles per slab (1..8) and attributes per slab (at most
+// kDsCap) that cover D with the fewest padded columns in total.
 void lp_slab_plan(int degree, int D, int* nts_out, int* ds_out, int* nslab_out) {
   const int m = basis_terms(degree), nmom = moment_terms(degree);
   int best_cost = 1 << 30, best_nts = 8, best_ds = 1, best_ns = D;
   for (int nts = 1; nts <= 8; ++nts) {
-    const int ds = (nts * 16 - nmom) / m;
+    int ds = (nts * 16 - nmom) / m;
+    if (ds > kDsCap) ds = kDsCap;
     if (ds < 1) continue;
     const int dsu = ds < D ? ds : D;
     const int ns = (D + dsu - 1) / dsu;
@@ -461,6 +547,12 @@ void lp_slab_plan(int degree, int D, int* nts_out, int* ds_out, int* nslab_out) 
   *nslab_out = best_ns;
 }
 
+// Largest node offset across a tile, in units of h.
+double lp_tile_extent(double dx, double dy, double h) {
+  const double ex = (double)(kCols - 1) * fabs(dx / h), ey = (double)(kRows - 1) * fabs(dy / h);
+  return ex > ey ? ex : ey;
+}
+
 hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shift,
                          const float* scale, bool fp16, int terms, const LPCells* cells,
                          hipStream_t stream) {
@@ -475,7 +567,6 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
   p.D = a.D;
   p.Ds = ds;
   p.nslab = nslab;
-  p.F = moment_terms(a.degree) + basis_terms(a.degree) * ds;
   p.inv_hd = 1.0 / a.h;
   p.inv_h = (float)p.inv_hd;
   p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;

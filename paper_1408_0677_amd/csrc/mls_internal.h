@@ -41,6 +41,8 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
                          const float* scale, bool fp16, int terms, const LPCells* cells,
                          hipStream_t stream);
 void lp_slab_plan(int degree, int D, int* nts, int* ds, int* nslab);
+// Largest node offset across a 16 x 16 node tile, in units of h.
+double lp_tile_extent(double dx, double dy, double h);
 
 // Attribute staging: partial ranges (stage_partial_blocks(n) x D floats in
 // pmin and pmax), shift/scale [D], attribute-major normalised copy [D][n].

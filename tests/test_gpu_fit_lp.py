@@ -1,0 +1,271 @@
+"""GPU parity of the 16-bit contraction paths (MLS_PREC_BF16 / FP16)
+against the FP64 oracle.
+
+These paths are lossy by design: every feature is carried as `lp_terms`
+16-bit terms, the weight as a hi + lo pair of 16-bit terms, and the moments
+are summed in float32 in a frame shared by a 16 x 16 node tile.  The stated
+bounds, per field, over the nodes where both sides agree on the degree and
+the oracle's smallest equilibrated pivot is >= 1e-2 (error relative to the
+attribute's input range), for tiles spanning at most the supported span
+(4 h linear, 2.5 h quadratic):
+  smooth attributes:  max <= LP_MAX[(precision, terms)], rms <= LP_RMS[...]
+  noise attributes:   max <= NOISY_MAX, rms <= NOISY_RMS
+The degree code may differ where a pivot lies within the contraction's
+error of the threshold; such nodes are counted (at most 2 % of the nodes),
+not compared.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from tests.parity import compare
+
+pytestmark = pytest.mark.gpu
+
+# (precision, terms) -> bound on the max / rms error over the d_min >= 1e-2 set
+LP_MAX = {("bf16", 3): 2e-3, ("fp16", 3): 2e-3, ("bf16", 2): 5e-2, ("fp16", 2): 5e-2}
+LP_RMS = {("bf16", 3): 1e-4, ("fp16", 3): 1e-4, ("bf16", 2): 1e-3, ("fp16", 2): 1e-3}
+NOISY_MAX, NOISY_RMS = 2e-2, 1e-3
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def gpu_fit(torch, pts, vals, grid, **kw):
+    from paper_1408_0677_amd import api
+    P = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+    V = torch.from_numpy(np.ascontiguousarray(vals, np.float32)).cuda()
+    f, d = api.fit(P, V, grid, **kw)
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), d.cpu().numpy()
+
+
+def check_lp(stats, prec, terms, mismatch_frac=0.02):
+    note(str({k: v for k, v in stats.items() if k != "per_field_max_pass"}))
+    assert stats["nan_ok"], stats
+    assert stats["nan_mismatch"] <= max(2, 1e-3 * stats["nodes"]), stats
+    assert stats["degree_mismatch"] <= max(2, mismatch_frac * stats["nodes"]), stats
+    assert stats["max_err_pass"] <= LP_MAX[(prec, terms)], stats
+    assert stats["rms_err_pass"] <= LP_RMS[(prec, terms)], stats
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_c1_full_grid_lp(torch_dev, oracle, prec):
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c1()
+    note(f"case c1 {prec}")
+    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis=w.basis, h=w.h,
+                     precision=prec)
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, h=w.h)
+    st = compare(F.reshape(w.d, -1), deg, of.reshape(w.d, -1), od, dm, w.values,
+                 dmin_pass=1e-2)
+    check_lp(st, prec, 3)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("basis", ["constant", "linear", "quadratic"])
+@pytest.mark.parametrize("shape", [(37, 29, 600, 3, 0.08), (50, 7, 900, 5, 0.06),
+                                   (1, 1, 400, 2, 0.1), (20, 18, 800, 70, 0.06),
+                                   (130, 40, 3000, 41, 0.05)])
+def test_ragged_lp(torch_dev, oracle, prec, basis, shape):
+    """Ragged tiles and chunks, attribute slabs (70 and 41 attributes), smooth
+    attributes with an offset (exercises the staging normalisation).  The
+    widest grid runs 4.4 h past the point cloud, where Gaussian weights fall
+    below float16's normal range without the fp16 weight factor."""
+    from paper_1408_0677_amd import workloads as wl
+    W, H, n, D, h = shape
+    note(f"case ragged lp {prec} basis={basis} W={W} H={H} n={n} D={D}")
+    rng = np.random.default_rng(W * 1000 + H + n)
+    pts = rng.random((n, 2)) * 0.6 + 0.2
+    vals = wl.smooth_fields(rng, pts, D) * 3.0 + 10.0
+    grid = {"x0": 0.25, "y0": 0.25, "dx": 0.006, "dy": 0.007, "width": W, "height": H}
+    F, deg = gpu_fit(torch_dev, pts, vals, grid, basis=basis, h=h, precision=prec)
+    of, od, dm = oracle.fit_grid(pts, vals, grid, basis=basis, h=h)
+    st = compare(F.reshape(D, -1), deg, of.reshape(D, -1), od, dm, vals.astype(np.float32),
+                 dmin_pass=1e-2)
+    check_lp(st, prec, 3)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_noisy_attributes_lp(torch_dev, oracle, prec):
+    """Pure-noise attributes are the hard case for a float32 accumulator (the
+    weighted sums cancel); the bound is looser and stated separately."""
+    W, H, n, D = 40, 30, 2000, 4
+    note(f"case noisy lp {prec}")
+    rng = np.random.default_rng(77)
+    pts = rng.random((n, 2))
+    vals = rng.standard_normal((n, D))
+    grid = {"x0": 0.3, "y0": 0.3, "dx": 0.01, "dy": 0.01, "width": W, "height": H}
+    for basis in ("linear", "quadratic"):
+        F, deg = gpu_fit(torch_dev, pts, vals, grid, basis=basis, h=0.06, precision=prec)
+        of, od, dm = oracle.fit_grid(pts, vals, grid, basis=basis, h=0.06)
+        st = compare(F.reshape(D, -1), deg, of.reshape(D, -1), od, dm,
+                     vals.astype(np.float32), dmin_pass=1e-2)
+        note(str({k: v for k, v in st.items() if k != "per_field_max_pass"}))
+        assert st["nan_ok"]
+        assert st["max_err_pass"] <= NOISY_MAX, st
+        assert st["rms_err_pass"] <= NOISY_RMS, st
+
+
+def test_coarse_grid_refused_lp(torch_dev):
+    """Tiles spanning more than 4 h (linear) or 2.5 h (quadratic) are refused
+    by the 16-bit paths, the constant basis has no limit, and the float64
+    path serves every span."""
+    import torch
+    from paper_1408_0677_amd import api
+    P = torch.rand(100, 2, device="cuda")
+    V = torch.rand(100, 2, device="cuda")
+    note("case lp coarse grid")
+    # span = 15 dx / h
+    for basis, ok_dx, bad_dx in (("linear", 0.052, 0.055), ("quadratic", 0.032, 0.035)):
+        for prec in ("bf16", "fp16"):
+            grid = {"x0": 0.0, "y0": 0.0, "dx": bad_dx, "dy": 0.01, "width": 11, "height": 11}
+            with pytest.raises(api.MlsError) as ei:
+                api.fit(P, V, grid, basis=basis, h=0.2, precision=prec)
+            assert "UNSUPPORTED" in str(ei.value)
+            grid["dx"] = ok_dx
+            F, _ = api.fit(P, V, grid, basis=basis, h=0.2, precision=prec)
+            assert torch.isfinite(F).any()
+            grid["dx"] = bad_dx
+            F, _ = api.fit(P, V, grid, basis=basis, h=0.2, precision="f64")
+            assert torch.isfinite(F).any()
+    grid = {"x0": 0.0, "y0": 0.0, "dx": 0.1, "dy": 0.1, "width": 11, "height": 11}
+    F, _ = api.fit(P, V, grid, basis="constant", h=0.2, precision="bf16")
+    assert torch.isfinite(F).any()
+    torch.cuda.synchronize()
+
+
+def test_terms_order_accuracy(torch_dev, oracle):
+    """More terms per feature -> smaller error (1 term is far too coarse for
+    the quadratic basis; 3 terms reach about float32 features)."""
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c2(grid_side=128, n=2000)
+    note("case lp terms 1..3")
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis="quadratic", h=0.06)
+    errs = []
+    for terms in (1, 2, 3):
+        F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis="quadratic", h=0.06,
+                         precision="bf16", lp_terms=terms)
+        st = compare(F.reshape(w.d, -1), deg, of.reshape(w.d, -1), od, dm, w.values,
+                     dmin_pass=1e-2)
+        note(f"terms={terms}: max {st['max_err_pass']:.3e} rms {st['rms_err_pass']:.3e}")
+        errs.append(st["rms_err_pass"])
+        if terms >= 2:
+            check_lp(st, "bf16", terms, mismatch_frac=0.05)
+    assert errs[2] < errs[1] < errs[0]
+
+
+def test_c3_full_size_sampled(torch_dev, oracle):
+    """The 2048^2 / N = 50,000 / D = 64 quadratic workload (four attribute
+    slabs) on sampled nodes and a 32 x 32 window."""
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c3()
+    note(f"case c3 sampled {w.name}")
+    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis=w.basis, h=w.h,
+                     precision="bf16")
+    W = w.grid["width"]
+    rng = np.random.default_rng(7)
+    win = (np.arange(1000, 1032)[:, None] * W + np.arange(900, 932)[None, :]).ravel()
+    pix = np.unique(np.concatenate([rng.choice(W * W, 600, replace=False), win]))
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, h=w.h,
+                                 pixels=pix)
+    st = compare(F.reshape(w.d, -1)[:, pix], deg.ravel()[pix], of, od, dm, w.values,
+                 dmin_pass=1e-2)
+    note("per-field max " + " ".join(f"{v:.1e}" for v in st["per_field_max_pass"]))
+    check_lp(st, "bf16", 3)
+
+
+def test_lp_deterministic(torch_dev):
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c2(grid_side=256)
+    note("case lp determinism")
+    a, da = gpu_fit(torch_dev, w.points, w.values, w.grid, basis="quadratic", h=w.h,
+                    precision="bf16")
+    b, db = gpu_fit(torch_dev, w.points, w.values, w.grid, basis="quadratic", h=w.h,
+                    precision="bf16")
+    assert np.array_equal(da, db)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# Compact support (Wendland C2) through the device cell list
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("basis", ["constant", "linear", "quadratic"])
+@pytest.mark.parametrize("case", [
+    # W, H, n, D, h, clustered, points outside the grid
+    (37, 29, 800, 3, 0.1, False, False),
+    (64, 48, 6000, 5, 0.05, True, False),
+    (20, 70, 1600, 2, 0.08, False, True),
+    (1, 1, 200, 1, 0.2, False, False),
+])
+def test_wendland_cells(torch_dev, oracle, prec, basis, case):
+    from paper_1408_0677_amd import workloads as wl
+    W, H, n, D, h, clustered, outside = case
+    note(f"case wendland {prec} basis={basis} W={W} H={H} n={n} D={D} h={h}")
+    rng = np.random.default_rng(n + W)
+    pts = wl.clustered_points(rng, n, n_clusters=4, sigma_lo=0.02, sigma_hi=0.06) \
+        if clustered else rng.random((n, 2))
+    if outside:
+        pts = pts * 1.6 - 0.3
+    vals = wl.smooth_fields(rng, pts, D)
+    grid = {"x0": 0.2, "y0": 0.15, "dx": 0.006, "dy": 0.005, "width": W, "height": H}
+    F, deg = gpu_fit(torch_dev, pts, vals, grid, basis=basis, weight="wendland", h=h,
+                     precision=prec)
+    of, od, dm = oracle.fit_grid(pts, vals, grid, basis=basis, weight="wendland", h=h)
+    st = compare(F.reshape(D, -1), deg, of.reshape(D, -1), od, dm, vals.astype(np.float32),
+                 dmin_pass=1e-2)
+    check_lp(st, prec, 3)
+
+
+def test_wendland_deterministic(torch_dev):
+    """The binning is a stable sort: reruns are bit-identical."""
+    from paper_1408_0677_amd import workloads as wl
+    rng = np.random.default_rng(3)
+    pts = wl.clustered_points(rng, 200_000)
+    vals = rng.standard_normal((200_000, 4))
+    grid = wl.pixel_grid(512)
+    note("case wendland determinism")
+    a, da = gpu_fit(torch_dev, pts, vals, grid, basis="quadratic", weight="wendland", h=0.01,
+                    precision="bf16")
+    b, db = gpu_fit(torch_dev, pts, vals, grid, basis="quadratic", weight="wendland", h=0.01,
+                    precision="bf16")
+    assert np.array_equal(da, db)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_c5_full_size_sampled(torch_dev, oracle):
+    """N = 10^6 clustered points, D = 16, Wendland h = 0.01, quadratic,
+    4096^2 nodes: sampled nodes plus a 32 x 32 window inside a cluster."""
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c5()
+    note(f"case c5 sampled {w.name}")
+    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis=w.basis, weight=w.weight,
+                     h=w.h, precision="bf16")
+    W = w.grid["width"]
+    rng = np.random.default_rng(11)
+    # a window around the densest node region: the node nearest to a cluster point
+    k = int(rng.integers(w.n))
+    r = int(w.points[k, 1] * W)
+    c = int(w.points[k, 0] * W)
+    r, c = min(max(r, 16), W - 17), min(max(c, 16), W - 17)
+    win = (np.arange(r - 16, r + 16)[:, None] * W + np.arange(c - 16, c + 16)[None, :]).ravel()
+    pix = np.unique(np.concatenate([rng.choice(W * W, 1500, replace=False), win]))
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, weight=w.weight,
+                                 h=w.h, pixels=pix)
+    st = compare(F.reshape(w.d, -1)[:, pix], deg.ravel()[pix], of, od, dm, w.values,
+                 dmin_pass=1e-2)
+    note("per-field max " + " ".join(f"{v:.1e}" for v in st["per_field_max_pass"]))
+    check_lp(st, "bf16", 3)

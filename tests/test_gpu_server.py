@@ -37,6 +37,9 @@ def make_requests(seed=0, count=12):
         pts = wl.mixture_points(rng, n, k=3) if q % 2 else rng.random((n, 2))
         vals = rng.standard_normal((n, d))
         h = float(np.sqrt(30.0 / (np.pi * n))) * (2.0 if weight == "wendland" else 1.0)
+        if prec != "f64":
+            # 16-bit paths take tiles of at most 2.5 h (quadratic) / 4 h
+            side = max(side, int(np.ceil(15.0 / (2.4 * h))))
         reqs.append(dict(pts=pts.astype(np.float32), vals=vals.astype(np.float32),
                          grid=wl.pixel_grid(side, side + q), basis=basis, precision=prec,
                          weight=weight, h=h))
