@@ -77,9 +77,13 @@ typedef enum {
  *  MLS_PREC_BF16: bfloat16 matrix-core contraction with float32
  *                 accumulation.  Attributes are normalised to [-1, 1], each
  *                 feature is carried as `lp_terms` bfloat16 terms (default
- *                 3, about 24 significant bits), the weight is rounded once
- *                 per (node, point) and shared by all features.
- *  MLS_PREC_FP16: the same with float16 terms.
+ *                 3, about 24 significant bits) and the weight as a hi + lo
+ *                 pair; the lo part multiplies every feature term but the
+ *                 last, so all features of a (node, point) pair see the
+ *                 same weight to about 24 bits (5 products per feature).
+ *  MLS_PREC_FP16: the same with float16 terms (default 2 terms, about 22
+ *                 bits; 3 products per feature).  Weights are scaled by
+ *                 2^15 internally to stay above float16's subnormals.
  */
 typedef enum {
   MLS_PREC_F64 = 0,
@@ -105,7 +109,8 @@ typedef struct {
   double pivot_tol;     /* tau: smallest accepted equilibrated pivot; 1e-8 */
   double weight_floor;  /* nodes with sum of weights below this are NaN; 1e-6 */
   int32_t lp_terms;     /* 16-bit terms per feature for MLS_PREC_BF16/FP16:
-                           1, 2 or 3; 0 selects 3 */
+                           1, 2 or 3; 0 selects the default (3 for
+                           bfloat16, 2 for float16) */
 } mls_solve_opts;
 
 typedef struct mls_context mls_context;

@@ -245,7 +245,7 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   if (!is_finite(grid->x0) || !is_finite(grid->y0) || !is_finite(grid->dx) || !is_finite(grid->dy))
     return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
   double tau = 1e-8, floor_w = 1e-6;
-  int terms = 3;
+  int terms = precision == MLS_PREC_FP16 ? 2 : 3;
   if (opts) {
     tau = opts->pivot_tol;
     floor_w = opts->weight_floor;
@@ -310,7 +310,7 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   const double span_max = basis == MLS_BASIS_QUADRATIC ? MLS_LP_MAX_TILE_SPAN_QUADRATIC
                           : basis == MLS_BASIS_LINEAR  ? MLS_LP_MAX_TILE_SPAN_LINEAR
                                                        : HUGE_VAL;
-  if (extent > span_max)
+  if (extent > span_max * (1.0 + 1e-12))
     return fail(MLS_ERR_UNSUPPORTED, "a 16 x 16 node tile spans %.2f h (> %.1f h for this "
                 "basis); use MLS_PREC_F64 for grids this coarse against h", extent, span_max);
   if (fp16) {

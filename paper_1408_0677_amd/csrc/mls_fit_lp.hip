@@ -11,11 +11,17 @@
 //     the rounding of what the previous terms left);
 //   - the weight is carried as w_hi + w_lo (two terms) when S >= 2;
 //   - the contraction issues, per feature tile, w_hi x g_s for every term
-//     plus w_lo x g_1, all into one float32 accumulator: the products are
-//     exact and each weight x feature product keeps far more bits than the
-//     float32 accumulator;
-//   - the same weight multiplies every feature of a (node, point) pair, so
-//     rounding it only perturbs the weight function;
+//     plus w_lo x g_s for every term but the last, all into one float32
+//     accumulator (the products are exact).  What is left out,
+//     w_hi g_{>S} and w_lo g_{>=S}, is about 2^-24 (bfloat16, S = 3) or
+//     2^-22 (float16, S = 2) of the product for every feature alike.  With
+//     w_lo x g_1 alone the product would carry w_lo (g - g_1), an error of
+//     2^-16 that differs from feature to feature: the moment matrix and the
+//     right-hand sides would no longer see one common weight, and the
+//     normal equations amplify such inconsistent errors by their
+//     conditioning;
+//   - the part of the weight below w_hi + w_lo is common to all features
+//     of a pair, so it only perturbs the weight function;
 //   - attributes are staged in [-1, 1] (mls_stage.hip) and mapped back.
 //
 // Work split.  A workgroup owns a 16 x 16 node tile and one slab of
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
             const vec8 b = *(const vec8*)(G + ((size_t)s * L::kFP + q * 16 + i) * KSH + ks + k8);
 #pragma unroll
             for (int t = 0; t < R; ++t) acc[t][q] = mfma16(ahi[t], b, acc[t][q]);
-            if (S >= 2 && s == 0) {
+            if (s + 1 < S) {
 #pragma unroll
               for (int t = 0; t < R; ++t) acc[t][q] = mfma16(alo[t], b, acc[t][q]);
             }
