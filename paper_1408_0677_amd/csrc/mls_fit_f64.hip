@@ -70,6 +70,13 @@ template <int DEG, int NT, int R>
 struct F64Layout {
   static constexpr int kRows = kWaves * R;
   static constexpr int kFP = NT * 16;                    // padded features
+  static constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
+  static constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
+  // most attributes NT feature tiles can hold, and the per-thread registers
+  // that hold one chunk of their values
+  static constexpr int kDMax = (kFP - nmom) / m;
+  static constexpr int kValRegs =
+      kDMax > 0 ? (KT * kDMax + kThreads - 1) / kThreads : 1;
   // chunk phase
   static constexpr int kUx = 0;                          // [KT] tile-frame u_x
   static constexpr int kUy = kUx + KT;                   // [KT]
@@ -118,73 +125,120 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     for (int q = 0; q < NT; ++q) acc[t][q] = doublex4{0.0, 0.0, 0.0, 0.0};
 
   const int D = p.D, F = p.F;
+  // padding features stay zero for the whole kernel
+  for (int e = tid; e < (L::kFP - F) * KS; e += kThreads) G[F * KS + e] = 0.0;
+
+  // Raw chunk data is prefetched into registers one chunk ahead, so that
+  // the global-memory latency overlaps the previous chunk's MFMA sweep.
+  float pf_x = 0.0f, pf_y = 0.0f;
+  float pf_v[L::kValRegs];
+  auto prefetch = [&](int64_t k0) {
+    const int kn = (int)((p.n - k0) < KT ? (p.n - k0) : KT);
+    if (tid < KT && tid < kn) {
+      pf_x = p.pts[2 * (k0 + tid)];
+      pf_y = p.pts[2 * (k0 + tid) + 1];
+    }
+    // consecutive threads read consecutive values of the chunk (coalesced)
+    const float* v = p.vals + k0 * (int64_t)D;
+#pragma unroll
+    for (int it = 0; it < L::kValRegs; ++it) {
+      const int e = tid + it * kThreads;
+      pf_v[it] = (e < kn * D) ? v[e] : 0.0f;
+    }
+  };
+  prefetch(0);
+
+  // Gaussian step factors of the tile (exp(-2 s^2) per node step)
+  const double sx = p.dx * p.inv_h, sy = p.dy * p.inv_h;
+  const double qx = exp(-2.0 * sx * sx), qy = exp(-2.0 * sy * sy);
+
   for (int64_t k0 = 0; k0 < p.n; k0 += KT) {
     const int kn = (int)((p.n - k0) < KT ? (p.n - k0) : KT);
     // 1. coordinates in the tile frame
     if (tid < KT) {
       double x = 0.0, y = 0.0;
       if (tid < kn) {
-        x = ((double)p.pts[2 * (k0 + tid)] - cx) * p.inv_h;
-        y = ((double)p.pts[2 * (k0 + tid) + 1] - cy) * p.inv_h;
+        x = ((double)pf_x - cx) * p.inv_h;
+        y = ((double)pf_y - cy) * p.inv_h;
       }
       ux[tid] = x;
       uy[tid] = y;
     }
     __syncthreads();
-    // 2a. separable Gaussian factors; points past n get weight 0
-    for (int e = tid; e < (kCols + L::kRows) * KT; e += kThreads) {
-      const int k = e % KT, row = e / KT;
-      double v = 0.0;
+    if (tid < 2 * KT) {
+      // 2a. separable Gaussian factors g_c = exp(-(u - e_c)^2), e_c = (c - c_mid) s,
+      //     for one point and one axis.  Start at the node nearest to u (the
+      //     largest factor) and step outwards: g_{c+1} / g_c = exp(2 s (u - e_c) - s^2),
+      //     and that ratio itself shrinks by exp(-2 s^2) per step, so every
+      //     exponent is <= 0 and three exponentials serve the whole row.
+      //     Points past n get weight 0.
+      const int k = tid & (KT - 1);
+      const bool xaxis = tid < KT;
+      const int cnt = xaxis ? kCols : L::kRows;
+      const int mid = cnt / 2;
+      const double s = xaxis ? sx : sy;
+      const double q = xaxis ? qx : qy;
+      double* g = xaxis ? gx : gy;
       if (k < kn) {
-        if (row < kCols) {
-          const double d = ux[k] - (double)(row - kCols / 2) * p.dx * p.inv_h;
-          v = exp(-(d * d));
-          gx[row * KS + k] = v;
-        } else {
-          const int rr = row - kCols;
-          const double d = uy[k] - (double)(rr - L::kRows / 2) * p.dy * p.inv_h;
-          v = exp(-(d * d));
-          gy[rr * KS + k] = v;
+        const double u = xaxis ? ux[k] : uy[k];
+        const double t = u / s + (double)mid;
+        int cs = (int)fmin(fmax(rint(t), 0.0), (double)(cnt - 1));
+        const double dc = u - (double)(cs - mid) * s;
+        double gv = exp(-(dc * dc));
+        g[cs * KS + k] = gv;
+        double r = exp(2.0 * s * dc - s * s);
+        double v = gv;
+        for (int c = cs + 1; c < cnt; ++c) {
+          v *= r;
+          r *= q;
+          g[c * KS + k] = v;
+        }
+        r = exp(-2.0 * s * dc - s * s);
+        v = gv;
+        for (int c = cs - 1; c >= 0; --c) {
+          v *= r;
+          r *= q;
+          g[c * KS + k] = v;
         }
       } else {
-        if (row < kCols) gx[row * KS + k] = 0.0;
-        else gy[(row - kCols) * KS + k] = 0.0;
+        for (int c = 0; c < cnt; ++c) g[c * KS + k] = 0.0;
+      }
+    } else {
+      // 2b. moment monomials of the tile-frame coordinates
+      for (int e = tid - 2 * KT; e < nmom * KT; e += kThreads - 2 * KT) {
+        const int k = e % KT, j = e / KT;
+        // exponents of monomial j (ordered by total degree, then by y power)
+        int t = 0;
+        while ((t + 1) * (t + 2) / 2 <= j) ++t;
+        const int b = j - t * (t + 1) / 2, a = t - b;
+        double v = 1.0;
+        for (int q = 0; q < a; ++q) v *= ux[k];
+        for (int q = 0; q < b; ++q) v *= uy[k];
+        G[j * KS + k] = v;
       }
     }
-    // 2b. moment monomials of the tile-frame coordinates
-    for (int e = tid; e < nmom * KT; e += kThreads) {
-      const int k = e % KT, j = e / KT;
-      // exponents of monomial j (ordered by total degree, then by y power)
-      int t = 0;
-      while ((t + 1) * (t + 2) / 2 <= j) ++t;
-      const int b = j - t * (t + 1) / 2, a = t - b;
-      double v = 1.0;
-      for (int q = 0; q < a; ++q) v *= ux[k];
-      for (int q = 0; q < b; ++q) v *= uy[k];
-      G[j * KS + k] = v;
-    }
-    // 2c. basis x attribute products; consecutive threads read consecutive
-    //     values of one point (coalesced)
-    for (int e = tid; e < KT * D; e += kThreads) {
-      const int k = e / D, d = e % D;
-      const double f = (k < kn) ? (double)p.vals[(k0 + k) * (int64_t)D + d] : 0.0;
-      const double bx = ux[k], by = uy[k];
-      G[(nmom + d) * KS + k] = f;
-      if (m >= 3) {
-        G[(nmom + D + d) * KS + k] = bx * f;
-        G[(nmom + 2 * D + d) * KS + k] = by * f;
-      }
-      if (m >= 6) {
-        G[(nmom + 3 * D + d) * KS + k] = bx * bx * f;
-        G[(nmom + 4 * D + d) * KS + k] = bx * by * f;
-        G[(nmom + 5 * D + d) * KS + k] = by * by * f;
+    // 2c. basis x attribute products from the prefetched values
+#pragma unroll
+    for (int it = 0; it < L::kValRegs; ++it) {
+      const int e = tid + it * kThreads;
+      if (e < KT * D) {
+        const int k = e / D, d = e - k * D;
+        const double f = (double)pf_v[it];
+        G[(nmom + d) * KS + k] = f;
+        if (m >= 3) {
+          const double bx = ux[k], by = uy[k];
+          G[(nmom + D + d) * KS + k] = bx * f;
+          G[(nmom + 2 * D + d) * KS + k] = by * f;
+          if (m >= 6) {
+            G[(nmom + 3 * D + d) * KS + k] = bx * bx * f;
+            G[(nmom + 4 * D + d) * KS + k] = bx * by * f;
+            G[(nmom + 5 * D + d) * KS + k] = by * by * f;
+          }
+        }
       }
     }
-    // padding features stay zero
-    for (int e = tid; e < (L::kFP - F) * KT; e += kThreads) {
-      const int k = e % KT, j = F + e / KT;
-      G[j * KS + k] = 0.0;
-    }
+    // next chunk's raw data: in flight during the MFMA sweep
+    if (k0 + KT < p.n) prefetch(k0 + KT);
     __syncthreads();
 
     // 3. MFMA sweep over the chunk
