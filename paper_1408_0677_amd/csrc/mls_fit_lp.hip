@@ -205,20 +205,6 @@ struct LPLayout {
   static_assert(kBytes <= 160 * 1024, "LDS budget");
 };
 
-// Exponents of the moment monomials (ordered by total degree, then by the
-// power of u_y): entry j is u_x^kMonoA[j] u_y^kMonoB[j].
-__constant__ int8_t kMonoA[15] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
-__constant__ int8_t kMonoB[15] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
-// basis term j of [1, ux, uy, ux^2, ux uy, uy^2]
-__constant__ int8_t kBasA[6] = {0, 1, 0, 2, 1, 0};
-__constant__ int8_t kBasB[6] = {0, 0, 1, 0, 1, 2};
-
-__device__ __forceinline__ float ipow(float x, int e) {
-  float r = 1.0f;
-  for (int q = 0; q < e; ++q) r *= x;
-  return r;
-}
-
 // Offset of node column c0 + col (row r0 + row) from the tile anchor, in
 // units of h, computed in float64 from the grid definition.
 __device__ __forceinline__ double node_offset_xd(const LPParams& p, int c0, int col, float cxr) {
@@ -269,12 +255,33 @@ __device__ __forceinline__ void raw_store(float* raw, int Ds, int pt,
   }
 }
 
+constexpr int kTabIt = (kCols + kRows) * KT / kProd;   // table entries per producer thread
+
+// Node offsets (in h, from the tile anchor) of the table rows a producer
+// thread fills: entry it is row (pt + it * kProd) / KT, a node column for
+// rows < 16 and a node row after that.
+__device__ __forceinline__ void table_offsets(const LPParams& p, int pt, int c0, int r0,
+                                              float cxr, float cyr, float (&toff)[kTabIt]) {
+#pragma unroll
+  for (int it = 0; it < kTabIt; ++it) {
+    const int row = (pt + it * kProd) / KT;
+    toff[it] = row < kCols ? (float)node_offset_xd(p, c0, row, cxr)
+                           : (float)node_offset_yd(p, r0, row - kCols, cyr);
+  }
+}
+
 // Producer: raw chunk (LDS) -> weight tables and feature terms (LDS).
+// Features: a thread owns a pair of consecutive points (pp = pt % 32) and
+// one eighth of the features (group g = pt / 32): it forms the monomials of
+// its two points once, then writes moment monomials j = g (mod 8) and the
+// basis x attribute products of attributes d = g (mod 8), each as S packed
+// 16-bit term pairs (one 32-bit LDS store per term).
 template <int DEG, int NTS, int S, typename T, bool WEND>
 __device__ __forceinline__ void make_chunk(const LPParams& p, const float* raw, int kn, int Ds,
-                                           float* tab, T* G, int pt, int c0, int r0, float cxr,
-                                           float cyr) {
+                                           float* tab, T* G, int pt, const float (&toff)[kTabIt],
+                                           float cxr, float cyr) {
   using L = LPLayout<DEG, NTS, S, T>;
+  typedef T T2 __attribute__((ext_vector_type(2)));
   constexpr int m = L::m, nmom = L::nmom;
   const float* rx = raw;
   const float* ry = raw + KT;
@@ -284,51 +291,68 @@ __device__ __forceinline__ void make_chunk(const LPParams& p, const float* raw, 
   // pair when the A operand is built).  Points past the chunk: Gaussian 0,
   // Wendland a distance beyond the support.
 #pragma unroll
-  for (int it = 0; it < (kCols + kRows) * KT / kProd; ++it) {
+  for (int it = 0; it < kTabIt; ++it) {
     const int e = pt + it * kProd;
     const int k = e & (KT - 1), row = e / KT;
     float v = WEND ? 4.0f : 0.0f;
     if (k < kn) {
-      float u;
-      if (row < kCols) u = (rx[k] - cxr) * p.inv_h - (float)node_offset_xd(p, c0, row, cxr);
-      else u = (ry[k] - cyr) * p.inv_h - (float)node_offset_yd(p, r0, row - kCols, cyr);
-      // the factor rides on the column table (the weight is gx * gy)
+      const float u = (row < kCols ? rx[k] - cxr : ry[k] - cyr) * p.inv_h - toff[it];
+      // the fp16 weight factor rides on the column table (the weight is gx * gy)
       v = WEND ? u * u : __expf(-u * u) * (row < kCols ? WeightGain<T>::value : 1.0f);
     }
     tab[row * KSF + k] = v;
   }
-  // features: items (feature j, point pair); S packed 32-bit writes each
-  const int F = nmom + m * Ds;
-  for (int e = pt; e < L::kFP * (KT / 2); e += kProd) {
-    const int kp = (e & (KT / 2 - 1)) * 2, j = e / (KT / 2);
-    float v[2] = {0.0f, 0.0f};
+  // features
+  const int pp = pt & 31, g = pt >> 5;
+  const int k0 = 2 * pp;
+  float mo[2][nmom];
 #pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-      const int k = kp + h2;
-      if (k < kn && j < F) {
-        const float ux = (rx[k] - cxr) * p.inv_h;
-        const float uy = (ry[k] - cyr) * p.inv_h;
-        if (ux * ux + uy * uy <= p.cutoff2) {
-          if (j < nmom) {
-            v[h2] = ipow(ux, kMonoA[j]) * ipow(uy, kMonoB[j]);
-          } else {
-            const int jj = j - nmom;
-            const int bj = jj / Ds, d = jj - bj * Ds;
-            v[h2] = ipow(ux, kBasA[bj]) * ipow(uy, kBasB[bj]) * rv[d * KT + k];
-          }
-        }
-      }
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const float ux = (rx[k0 + h2] - cxr) * p.inv_h;
+    const float uy = (ry[k0 + h2] - cyr) * p.inv_h;
+    // points beyond the reach of every node of the tile get no features
+    const float one = (ux * ux + uy * uy <= p.cutoff2) ? 1.0f : 0.0f;
+    mo[h2][0] = one;
+    if (nmom > 1) {
+      mo[h2][1] = one * ux;
+      mo[h2][2] = one * uy;
+      mo[h2][3] = mo[h2][1] * ux;
+      mo[h2][4] = mo[h2][1] * uy;
+      mo[h2][5] = mo[h2][2] * uy;
     }
-    float r0v = v[0], r1v = v[1];
+    if (nmom > 6) {
+      mo[h2][6] = mo[h2][3] * ux;
+      mo[h2][7] = mo[h2][3] * uy;
+      mo[h2][8] = mo[h2][4] * uy;
+      mo[h2][9] = mo[h2][5] * uy;
+      mo[h2][10] = mo[h2][6] * ux;
+      mo[h2][11] = mo[h2][6] * uy;
+      mo[h2][12] = mo[h2][7] * uy;
+      mo[h2][13] = mo[h2][8] * uy;
+      mo[h2][14] = mo[h2][9] * uy;
+    }
+  }
+  auto emit = [&](int j, float v0, float v1) {
+    T* dst = G + (size_t)j * KSH + k0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const T t0 = (T)r0v, t1 = (T)r1v;
-      r0v -= (float)t0;
-      r1v -= (float)t1;
-      T* dst = G + ((size_t)s * L::kFP + j) * KSH + kp;
-      dst[0] = t0;
-      dst[1] = t1;
+      const T t0 = (T)v0, t1 = (T)v1;
+      v0 -= (float)t0;
+      v1 -= (float)t1;
+      T2 pr;
+      pr.x = t0;
+      pr.y = t1;
+      *(T2*)(dst + (size_t)s * L::kFP * KSH) = pr;
     }
+  };
+#pragma unroll
+  for (int j = 0; j < nmom; ++j)
+    if ((j & 7) == g) emit(j, mo[0][j], mo[1][j]);
+  // basis term bj is monomial bj
+  for (int d = g; d < Ds; d += 8) {
+    const float a0 = rv[d * KT + k0], a1 = rv[d * KT + k0 + 1];
+#pragma unroll
+    for (int bj = 0; bj < m; ++bj) emit(nmom + bj * Ds + d, mo[0][bj] * a0, mo[1][bj] * a1);
   }
 }
 
@@ -364,6 +388,20 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   Chunk ch0 = walker_take<CELLS>(p, wk);
   Chunk ch1 = walker_take<CELLS>(p, wk);
 
+  // feature rows past this slab's F are never written: zero them once in
+  // both buffers
+  {
+    const int Fs = L::nmom + L::m * Ds;
+    const int pad = (L::kFP - Fs) * KSH;
+    for (int b = 0; b < 2; ++b)
+      for (int s = 0; s < S; ++s) {
+        T* z = feat(b) + ((size_t)s * L::kFP + Fs) * KSH;
+        for (int e = tid; e < pad; e += kThreads) z[e] = (T)0.0f;
+      }
+  }
+  float toff[kTabIt];
+  if (!mma) table_offsets(p, pt, c0, r0, cxr, cyr, toff);
+
   // prologue: raw 0 and 1 to LDS, then chunk 0's tables and features
   float rr[L::kRawIt];
   if (!mma) {
@@ -374,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   }
   __syncthreads();
   if (!mma && ch0.valid)
-    make_chunk<DEG, NTS, S, T, WEND>(p, raw(0), ch0.kn, Ds, tab(0), feat(0), pt, c0, r0, cxr, cyr);
+    make_chunk<DEG, NTS, S, T, WEND>(p, raw(0), ch0.kn, Ds, tab(0), feat(0), pt, toff, cxr, cyr);
   __syncthreads();
 
   floatx4 acc[R][NTS];
@@ -428,7 +466,7 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
       raw_load<DEG, NTS, S, T>(p, ch2, d0, Ds, pt, rr);      // chunk c + 2, in flight
       if (ch1.valid)
         make_chunk<DEG, NTS, S, T, WEND>(p, raw((c + 1) & 1), ch1.kn, Ds, tab((c + 1) & 1),
-                                         feat((c + 1) & 1), pt, c0, r0, cxr, cyr);
+                                         feat((c + 1) & 1), pt, toff, cxr, cyr);
       raw_store<DEG, NTS, S, T>(raw(c & 1), Ds, pt, rr);
     }
     __syncthreads();
