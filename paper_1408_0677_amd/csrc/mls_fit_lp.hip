@@ -29,8 +29,10 @@
 // basis x attribute products for its D_s attributes, at most 16 NTS
 // columns, so the per-node accumulators fit in registers.  Every slab
 // repeats the moments, which lets each slab solve its own nodes.
-// Eight waves: waves 0-3 issue the matrix instructions (each owns 4 row
-// strips x NTS feature tiles of 16 x 16 float32), waves 4-7 produce.  Points
+// Twelve waves: waves 0-7 issue the matrix instructions (each owns 2 row
+// strips x NTS feature tiles of 16 x 16 float32), waves 8-11 produce.  Two
+// matrix waves per SIMD let one wave build its weight operands while the
+// other's MFMAs run.  Points
 // stream in chunks of 64 through a three-stage pipeline, one barrier per
 // chunk:
 //   producers, iteration c:  load the raw chunk c + 2 (coordinates, staged
@@ -57,11 +59,14 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-constexpr int kMmaWaves = 4;
+#ifndef MLS_LP_MMA_WAVES
+#define MLS_LP_MMA_WAVES 8
+#endif
+constexpr int kMmaWaves = MLS_LP_MMA_WAVES;
 constexpr int kProd = 256;                 // producer threads
 constexpr int kThreads = kMmaWaves * 64 + kProd;
 constexpr int kCols = 16;
-constexpr int R = 4;                       // row strips per MFMA wave
+constexpr int R = 16 / kMmaWaves;          // row strips per MFMA wave
 constexpr int kRows = kMmaWaves * R;       // 16
 constexpr int KT = 64;                     // points per chunk (two MFMA k-steps)
 constexpr int KSF = KT + 4;                // float32 table stride (floats)
