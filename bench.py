@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_F64_MFMA_TFLOPS = 78.6     # MI355X dense float64 matrix peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense bfloat16 / float16 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -39,21 +40,91 @@ def basis_terms(basis):
     return {"constant": 1, "linear": 3, "quadratic": 6}[basis]
 
 
-def cpu_baseline(w, row_stride=16):
-    """The oracle on every row_stride-th grid row of the same workload."""
+def cpu_baseline(w, row_stride=1, precision_note="FP64"):
+    """The oracle on every row_stride-th grid row of the same workload,
+    with the host's threads (at most 16)."""
     from oracle import oracle
     W, H = w.grid["width"], w.grid["height"]
     rows = np.arange(0, H, row_stride)
     pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel()
     threads = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
-    oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, h=w.h, pixels=pix,
-                    threads=threads)
+    oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, weight=w.weight, h=w.h,
+                    pixels=pix, threads=threads)
     dt = time.perf_counter() - t0
-    pairs = pix.size * w.n
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {row_stride}th row of the {W}x{H} grid ({pix.size} nodes x "
-                      f"{w.n} points), FP64, {dt:.2f} s"}
+    if w.weight == "wendland":
+        pairs = support_pairs(w.points, w.grid, w.h, rows=rows)
+        what = "node-point pairs inside the support"
+    else:
+        pairs = pix.size * w.n
+        what = "node-point pairs"
+    sample = (f"all {H} rows" if row_stride == 1 else f"every {row_stride}th row") + \
+        f" of the {W}x{H} grid ({pix.size} nodes x {w.n} points), {precision_note}, {dt:.2f} s"
+    return {"value": pairs / dt, "unit": f"pairs/s ({what})", "cores": threads,
+            "kind": "oracle", "sample": sample}
+
+
+def support_pairs(points, grid, h, rows=None):
+    """Number of (node, point) pairs with |node - point| < h (the pairs a
+    compactly supported weight leaves), counted per point and node row."""
+    x0, y0, dx, dy = grid["x0"], grid["y0"], grid["dx"], grid["dy"]
+    W, H = grid["width"], grid["height"]
+    px = points[:, 0].astype(np.float64)
+    py = points[:, 1].astype(np.float64)
+    row_ok = np.zeros(H, dtype=bool)
+    row_ok[np.arange(H) if rows is None else rows] = True
+    r_lo = np.ceil((py - h - y0) / dy).astype(np.int64)
+    span = int(np.ceil(2 * h / abs(dy))) + 2
+    total = 0
+    for k in range(span + 1):
+        r = r_lo + k
+        ok = (r >= 0) & (r < H)
+        r_c = np.clip(r, 0, H - 1)
+        ok &= row_ok[r_c]
+        ddy = y0 + r_c * dy - py
+        rem = h * h - ddy * ddy
+        ok &= rem > 0
+        half = np.sqrt(np.where(ok, rem, 0.0))
+        c_lo = np.maximum(np.floor((px - half - x0) / dx).astype(np.int64) + 1, 0)
+        c_hi = np.minimum(np.ceil((px + half - x0) / dx).astype(np.int64) - 1, W - 1)
+        total += int(np.where(ok, np.maximum(c_hi - c_lo + 1, 0), 0).sum())
+    return total
+
+
+def source_digest(paths):
+    import hashlib
+    hsh = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            hsh.update(f.read())
+    return hsh.hexdigest()
+
+
+def profiled_traffic(summary, sources):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    from the kernel sources as they are now; else None."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":", 1)[0].strip() in (
+                    "traffic_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_sha256") != source_digest(sources):
+        return None
+    try:
+        return int(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+F64_SOURCES = ["paper_1408_0677_amd/csrc/mls_fit_f64.hip", "paper_1408_0677_amd/csrc/mls_solve.h",
+               "paper_1408_0677_amd/csrc/mls_internal.h"]
+LP_SOURCES = ["paper_1408_0677_amd/csrc/mls_fit_lp.hip", "paper_1408_0677_amd/csrc/mls_solve.h",
+              "paper_1408_0677_amd/csrc/mls_internal.h"]
 
 
 def serve_bench(args):
@@ -131,8 +202,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2: the 1024^2 fit + contour step (default); c4: the served "
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the 1024^2 float64 fit + contour step (default); c3: the "
+                         "2048^2 / D = 64 quadratic bfloat16 fit; c5: the 4096^2 / "
+                         "N = 10^6 Wendland bfloat16 fit + contour; c4: the served "
                          "request mix with Poisson arrivals")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
@@ -150,23 +223,43 @@ def main():
         print(json.dumps(serve_bench(args)), flush=True)
         return
 
-    w = wl.c2()
+    if args.workload == "c2":
+        w, prec = wl.c2(), "f64"
+    elif args.workload == "c3":
+        w, prec = wl.c3(), "bf16"
+    else:
+        w, prec = wl.c5(), "bf16"
+    out = fit_step_bench(args, w, prec)
+    print(json.dumps(out), flush=True)
+
+
+def fit_step_bench(args, w, prec):
+    """One step = mls_fit over the whole grid, then mls_contour over every
+    field if the workload has isovalues; inputs resident in HBM."""
+    import torch
+    from paper_1408_0677_amd import api
+
     dev = torch.device("cuda:0")
     P = torch.from_numpy(w.points).to(dev)
     V = torch.from_numpy(w.values).to(dev)
-    iso = torch.from_numpy(w.iso()).to(dev)
+    iso = torch.from_numpy(w.iso()).to(dev) if w.n_iso else None
     W, H = w.grid["width"], w.grid["height"]
     fields = torch.empty((w.d, H, W), dtype=torch.float32, device=dev)
     degree = torch.empty((H, W), dtype=torch.uint8, device=dev)
     ctx = api.default_context(0)
     stream = torch.cuda.current_stream()
+    kw = dict(basis=w.basis, weight=w.weight, h=w.h, precision=prec, out=fields,
+              degree_out=degree, ctx=ctx, stream=stream)
 
     # size the segment buffer once (outside the timed region)
-    api.fit(P, V, w.grid, basis=w.basis, h=w.h, out=fields, degree_out=degree, ctx=ctx,
-            stream=stream)
-    segs0, _, _ = api.contour(fields, w.grid, iso, ctx=ctx, stream=stream)
-    capacity = int(segs0.shape[0] * 1.25) + 1024
-    seg_count = int(segs0.shape[0])
+    api.fit(P, V, w.grid, **kw)
+    capacity = 0
+    seg_count = 0
+    if iso is not None:
+        segs0, _, _ = api.contour(fields, w.grid, iso, want_cases=False, ctx=ctx,
+                                  stream=stream)
+        capacity = int(segs0.shape[0] * 1.25) + 1024
+        seg_count = int(segs0.shape[0])
 
     fit_ev = []
 
@@ -174,13 +267,15 @@ def main():
         if timed:
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-        api.fit(P, V, w.grid, basis=w.basis, h=w.h, out=fields, degree_out=degree,
-                ctx=ctx, stream=stream)
+        api.fit(P, V, w.grid, **kw)
         if timed:
             b.record(stream)
             fit_ev.append((a, b))
-        api.contour(fields, w.grid, iso, capacity=capacity, want_ids=True, ctx=ctx,
-                    stream=stream)
+        if iso is not None:
+            # the product is the segments and their (field, iso, cell) ids; the
+            # per-(cell, iso) case bytes are an optional output left off here
+            api.contour(fields, w.grid, iso, want_cases=False, capacity=capacity,
+                        want_ids=True, ctx=ctx, stream=stream)
 
     for _ in range(args.warmup):
         step(False)
@@ -192,6 +287,8 @@ def main():
     for _ in range(args.steps):
         ts = time.perf_counter()
         step(True)            # mls_contour returns after the stream has delivered its count
+        if iso is None:
+            torch.cuda.current_stream().synchronize()
         step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -205,15 +302,32 @@ def main():
         torch.cuda.synchronize()
 
     nodes = W * H
-    pairs = nodes * w.n
     F = moment_terms(w.basis) + basis_terms(w.basis) * w.d
+    if w.weight == "wendland":
+        pairs = support_pairs(w.points, w.grid, w.h)
+        pair_kind = "node-point pairs inside the support"
+    else:
+        pairs = nodes * w.n
+        pair_kind = "node-point pairs"
     flops = 2.0 * F * pairs
     ms_per_step = wall * 1e3 / args.steps
-    kern_ms = float(np.mean(fit_ms))   # one fit kernel launch per step
+    # the fit is one launch of the contraction kernel plus small staging
+    # kernels; the events bracket the whole call
+    kern_ms = float(np.mean(fit_ms))
     achieved = flops / (kern_ms * 1e-3) / 1e12
+    if prec == "f64":
+        peak, kernel, sources = PEAK_F64_MFMA_TFLOPS, "fit_f64_kernel", F64_SOURCES
+        summary = "fit_f64_c2_1024_traffic.md"
+    else:
+        peak, kernel, sources = PEAK_BF16_MFMA_TFLOPS, "fit_lp_kernel", LP_SOURCES
+        summary = f"fit_lp_{args.workload}_traffic.md"
+    traffic = profiled_traffic(summary, sources)
 
+    metric = ("MLS pixel·point pairs/s and fields/s at 1024² grid; p50/p99 fit latency"
+              if args.workload == "c2" else
+              f"MLS pixel·point pairs/s and fields/s ({args.workload}); p50/p99 fit latency")
     out = {
-        "metric": "MLS pixel·point pairs/s and fields/s at 1024² grid; p50/p99 fit latency",
+        "metric": metric,
         "value": pairs * args.steps / wall,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -223,26 +337,34 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": prec,
         "data": "synthetic",
         "config": {"workload": w.name, "nodes": nodes, "points": w.n, "attributes": w.d,
-                   "basis": w.basis, "weight": "gaussian", "h": w.h,
-                   "contraction": "f64 mfma", "solve": "f64", "isovalues_per_field": w.n_iso,
+                   "basis": w.basis, "weight": w.weight, "h": w.h, "pairs": pairs,
+                   "pair_kind": pair_kind,
+                   "contraction": "f64 mfma" if prec == "f64" else
+                                  f"{prec} mfma, float32 accumulation",
+                   "solve": "f64", "isovalues_per_field": w.n_iso,
                    "segments": seg_count},
         "fields_per_s": w.d * args.steps / wall,
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                        "p99": float(np.percentile(step_ms, 99)),
                        "fit_p50": float(np.percentile(fit_ms, 50)),
                        "fit_p99": float(np.percentile(fit_ms, 99))},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
-                     "traffic": None, "kernel": "fit_f64_kernel",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic, "kernel": kernel,
                      "algorithmic_flops_per_launch": flops,
                      "kernel_ms": kern_ms},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(out), flush=True)
+        if args.workload == "c2":
+            out["cpu_baseline"] = cpu_baseline(w, row_stride=1)
+        elif args.workload == "c3":
+            out["cpu_baseline"] = cpu_baseline(w, row_stride=128)
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, row_stride=1024)
+    return out
 
 
 if __name__ == "__main__":

@@ -435,8 +435,7 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
   const int64_t entries = mls::contour_scratch_entries(d, n_iso, grid->width, grid->height);
   const int64_t tiles = mls::contour_scan_tiles(entries);
   const size_t off_counts = 0;
-  const size_t off_offsets = align_up(sizeof(int32_t) * (size_t)entries, 256);
-  const size_t off_tiles = off_offsets + align_up(sizeof(int64_t) * (size_t)entries, 256);
+  const size_t off_tiles = align_up(sizeof(int32_t) * (size_t)entries, 256);
   const size_t off_total = off_tiles + align_up(sizeof(int64_t) * (size_t)tiles, 256);
   const size_t need = off_total + 256;
   if ((st = ensure_scratch(ctx->scratch, need)) != MLS_OK) return st;
@@ -465,7 +464,7 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
   a.ids = d_seg_ids;
   a.capacity = capacity;
   a.counts = (int32_t*)(base + off_counts);
-  a.offsets = (int64_t*)(base + off_offsets);
+  a.offsets = a.counts;   // scanned in place
   a.tile_sums = (int64_t*)(base + off_tiles);
   a.total = (int64_t*)(base + off_total);
   hipStream_t s = (hipStream_t)stream;

@@ -13,11 +13,19 @@
 //
 // Three passes keep the output in (field, iso, cell, segment) order without
 // atomics, so it is deterministic:
-//   count:  one thread per cell, all isovalues of one field per block
-//           (the four corners are loaded once), per-block segment counts;
-//   scan:   exclusive scan of the counts in (field, iso, block) order;
-//   emit:   recompute, block-local prefix sum, write segments and ids.
-// The work is bound by reading the fields once per pass (HBM).
+//   count:  a wave owns a chunk of 256 consecutive cells of one field (four
+//           per lane, lane l holding cells l, l + 64, l + 128, l + 192, so
+//           the corner loads coalesce) and visits every isovalue with the
+//           corners in registers; the chunk's segment count per isovalue is
+//           two ballots and two population counts per cell group, with no
+//           shuffles and no barriers.  An isovalue outside every lane's
+//           [min, max] corner range is skipped with one wave-wide test;
+//   scan:   exclusive scan of the counts in (field, iso, chunk) order;
+//   emit:   recompute; a segment's slot is the chunk's scanned offset plus
+//           the ballot prefix of the cells before it, then write segments
+//           and ids.
+// Reading the fields is one pass of HBM traffic per kernel; with many
+// isovalues the per-(cell, iso) tests dominate (vector ALU).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,7 +34,9 @@
 namespace mls {
 namespace {
 
-constexpr int kCellsPerBlock = 256;
+constexpr int kCellsPerLane = 4;
+constexpr int kCellsPerWave = 64 * kCellsPerLane;   // one count entry per wave chunk
+constexpr int kWavesPerBlock = 4;
 constexpr int kScanTile = 1024;      // entries per block of the first scan level
 
 // Segments per case: from-edge, to-edge pairs; cases 5 and 10 are resolved
@@ -108,38 +118,16 @@ __device__ __forceinline__ void edge_point(int e, const Corners& c, float iso, i
   *y = (float)py;
 }
 
-// Block-wide exclusive sum of one int per thread (256 threads).
-__device__ __forceinline__ int block_exclusive_sum(int v, int* total, int* scratch) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int n = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += n;
-  }
-  if (lane == 63) scratch[wave] = incl;
-  __syncthreads();
-  int base = 0, sum = 0;
-#pragma unroll
-  for (int w = 0; w < kCellsPerBlock / 64; ++w) {
-    const int s = scratch[w];
-    if (w < wave) base += s;
-    sum += s;
-  }
-  __syncthreads();
-  *total = sum;
-  return base + incl - v;
-}
-
 struct ContourParams {
   const float* fields;
   const float* iso;      // [D][n_iso]
   int D, n_iso, W, H;
   int64_t cells;         // (H - 1) * (W - 1)
-  int64_t nchunk;        // blocks per field
+  int64_t nchunk;        // wave chunks (of kCellsPerWave cells) per field
+  int64_t bpf;           // blocks per field
   uint8_t* cases;        // [D][n_iso][cells] or null
   int32_t* counts;       // [D][n_iso][nchunk]
-  int64_t* offsets;      // [D][n_iso][nchunk], exclusive within scan tiles
+  const int32_t* offsets;  // [D][n_iso][nchunk], exclusive within scan tiles
   const int64_t* tile_prefix;  // exclusive prefix of scan tiles
   float* segs;           // [cap][4]
   int32_t* ids;          // [cap][3] or null
@@ -147,33 +135,75 @@ struct ContourParams {
   GridD g;
 };
 
-__global__ __launch_bounds__(kCellsPerBlock) void contour_count_kernel(ContourParams p) {
-  __shared__ int scratch[kCellsPerBlock / 64];
-  const int d = blockIdx.x / p.nchunk;
-  const int64_t chunk = blockIdx.x % p.nchunk;
-  const int64_t cell = chunk * kCellsPerBlock + threadIdx.x;
-  const bool in = cell < p.cells;
+// The cells of one wave chunk: corners in registers, and the range of the
+// lane's valid corners (an isovalue outside it crosses none of them).
+struct WaveCells {
+  Corners c[kCellsPerLane];
+  int i[kCellsPerLane], j[kCellsPerLane];
+  int64_t cell[kCellsPerLane];
+  bool in[kCellsPerLane];
+  float lo, hi;
+};
+
+__device__ __forceinline__ void load_wave_cells(const ContourParams& p, const float* f,
+                                                int64_t chunk, int lane, WaveCells& w) {
   const int cw = p.W - 1;
-  Corners c = {0.f, 0.f, 0.f, 0.f, false};
-  int i = 0, j = 0;
-  const float* f = p.fields + (int64_t)d * p.W * p.H;
-  if (in) {
-    i = (int)(cell / cw);
-    j = (int)(cell % cw);
-    c = load_corners(f, p.W, i, j);
-  }
-  for (int k = 0; k < p.n_iso; ++k) {
-    const float iso = p.iso[d * p.n_iso + k];
-    const int cs = in ? cell_case(c, iso) : 255;
-    if (in && p.cases) p.cases[((int64_t)d * p.n_iso + k) * p.cells + cell] = (uint8_t)cs;
-    int total;
-    block_exclusive_sum(in ? segment_count(cs) : 0, &total, scratch);
-    if (threadIdx.x == 0) p.counts[((int64_t)d * p.n_iso + k) * p.nchunk + chunk] = total;
+  w.lo = __builtin_inff();
+  w.hi = -__builtin_inff();
+#pragma unroll
+  for (int q = 0; q < kCellsPerLane; ++q) {
+    const int64_t cell = chunk * kCellsPerWave + q * 64 + lane;
+    w.cell[q] = cell;
+    w.in[q] = cell < p.cells;
+    w.c[q] = Corners{0.f, 0.f, 0.f, 0.f, false};
+    w.i[q] = w.j[q] = 0;
+    if (w.in[q]) {
+      w.i[q] = (int)(cell / cw);
+      w.j[q] = (int)(cell % cw);
+      w.c[q] = load_corners(f, p.W, w.i[q], w.j[q]);
+      if (w.c[q].valid) {
+        w.lo = fminf(w.lo, fminf(fminf(w.c[q].v0, w.c[q].v1), fminf(w.c[q].v2, w.c[q].v3)));
+        w.hi = fmaxf(w.hi, fmaxf(fmaxf(w.c[q].v0, w.c[q].v1), fmaxf(w.c[q].v2, w.c[q].v3)));
+      }
+    }
   }
 }
 
-// First scan level: exclusive scan inside tiles of kScanTile entries.
-__global__ __launch_bounds__(256) void scan_tiles_kernel(const int32_t* in, int64_t* out,
+__global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(ContourParams p) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int d = (int)(blockIdx.x / p.bpf);
+  const int64_t chunk = (blockIdx.x % p.bpf) * kWavesPerBlock + wave;
+  if (chunk >= p.nchunk) return;   // whole wave; the kernel has no barrier
+  const float* f = p.fields + (int64_t)d * p.W * p.H;
+  WaveCells w;
+  load_wave_cells(p, f, chunk, lane, w);
+  for (int k = 0; k < p.n_iso; ++k) {
+    const float iso = p.iso[d * p.n_iso + k];
+    int64_t count = 0;
+    if (p.cases) {
+#pragma unroll
+      for (int q = 0; q < kCellsPerLane; ++q)
+        if (w.in[q])
+          p.cases[((int64_t)d * p.n_iso + k) * p.cells + w.cell[q]] =
+              (uint8_t)cell_case(w.c[q], iso);
+    }
+    // a cell has segments iff min < iso <= max over its corners
+    if (__any(iso > w.lo && iso <= w.hi)) {
+#pragma unroll
+      for (int q = 0; q < kCellsPerLane; ++q) {
+        const int ns = w.in[q] ? segment_count(cell_case(w.c[q], iso)) : 0;
+        count += __popcll(__ballot(ns >= 1)) + __popcll(__ballot(ns == 2));
+      }
+    }
+    if (lane == 0) p.counts[((int64_t)d * p.n_iso + k) * p.nchunk + chunk] = (int32_t)count;
+  }
+}
+
+// First scan level: exclusive scan inside tiles of kScanTile entries (a
+// tile holds at most kScanTile * 2 * kCellsPerWave segments, so int32
+// offsets suffice).  `out` may alias `in`: every thread reads its four
+// entries before it writes them.
+__global__ __launch_bounds__(256) void scan_tiles_kernel(const int32_t* in, int32_t* out,
                                                          int64_t* tile_sums, int64_t n) {
   __shared__ int64_t wsum[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -204,7 +234,7 @@ __global__ __launch_bounds__(256) void scan_tiles_kernel(const int32_t* in, int6
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t idx = base + 4 * t + q;
-    if (idx < n) out[idx] = run;
+    if (idx < n) out[idx] = (int32_t)run;
     run += v[q];
   }
   if (t == 0) tile_sums[blockIdx.x] = tot;
@@ -241,42 +271,40 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t* sums, int64_t 
   if (t == 0) *total = tot;
 }
 
-__global__ __launch_bounds__(kCellsPerBlock) void contour_emit_kernel(ContourParams p) {
-  __shared__ int scratch[kCellsPerBlock / 64];
-  const int d = blockIdx.x / p.nchunk;
-  const int64_t chunk = blockIdx.x % p.nchunk;
-  const int64_t cell = chunk * kCellsPerBlock + threadIdx.x;
-  const bool in = cell < p.cells;
-  const int cw = p.W - 1;
-  Corners c = {0.f, 0.f, 0.f, 0.f, false};
-  int i = 0, j = 0;
+__global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(ContourParams p) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int d = (int)(blockIdx.x / p.bpf);
+  const int64_t chunk = (blockIdx.x % p.bpf) * kWavesPerBlock + wave;
+  if (chunk >= p.nchunk) return;
   const float* f = p.fields + (int64_t)d * p.W * p.H;
-  if (in) {
-    i = (int)(cell / cw);
-    j = (int)(cell % cw);
-    c = load_corners(f, p.W, i, j);
-  }
+  WaveCells w;
+  load_wave_cells(p, f, chunk, lane, w);
+  const uint64_t below = (1ull << lane) - 1ull;   // lanes before this one
   for (int k = 0; k < p.n_iso; ++k) {
-    const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
     const float iso = p.iso[d * p.n_iso + k];
-    const int cs = in ? cell_case(c, iso) : 255;
-    int seg[2][2];
-    const int ns = in ? case_segments(cs, c, iso, seg) : 0;
-    int total;
-    const int local = block_exclusive_sum(ns, &total, scratch);
-    if (total == 0) continue;
-    const int64_t base = p.offsets[slot] + p.tile_prefix[slot / kScanTile] + local;
-    for (int q = 0; q < ns; ++q) {
-      const int64_t o = base + q;
-      if (o >= p.capacity) break;
-      float x0, y0, x1, y1;
-      edge_point(seg[q][0], c, iso, i, j, p.g, &x0, &y0);
-      edge_point(seg[q][1], c, iso, i, j, p.g, &x1, &y1);
-      reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
-      if (p.ids) {
-        p.ids[3 * o] = d;
-        p.ids[3 * o + 1] = k;
-        p.ids[3 * o + 2] = (int32_t)cell;
+    if (!__any(iso > w.lo && iso <= w.hi)) continue;
+    const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
+    int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
+#pragma unroll
+    for (int q = 0; q < kCellsPerLane; ++q) {
+      const int cs = w.in[q] ? cell_case(w.c[q], iso) : 255;
+      int seg[2][2];
+      const int ns = w.in[q] ? case_segments(cs, w.c[q], iso, seg) : 0;
+      const uint64_t one = __ballot(ns >= 1), two = __ballot(ns == 2);
+      const int64_t base = run + __popcll(one & below) + __popcll(two & below);
+      run += __popcll(one) + __popcll(two);
+      for (int s2 = 0; s2 < ns; ++s2) {
+        const int64_t o = base + s2;
+        if (o >= p.capacity) break;
+        float x0, y0, x1, y1;
+        edge_point(seg[s2][0], w.c[q], iso, w.i[q], w.j[q], p.g, &x0, &y0);
+        edge_point(seg[s2][1], w.c[q], iso, w.i[q], w.j[q], p.g, &x1, &y1);
+        reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
+        if (p.ids) {
+          p.ids[3 * o] = d;
+          p.ids[3 * o + 1] = k;
+          p.ids[3 * o + 2] = (int32_t)w.cell[q];
+        }
       }
     }
   }
@@ -286,7 +314,7 @@ __global__ __launch_bounds__(kCellsPerBlock) void contour_emit_kernel(ContourPar
 
 int64_t contour_scratch_entries(int32_t D, int32_t n_iso, int32_t W, int32_t H) {
   const int64_t cells = (int64_t)(W - 1) * (H - 1);
-  const int64_t nchunk = (cells + kCellsPerBlock - 1) / kCellsPerBlock;
+  const int64_t nchunk = (cells + kCellsPerWave - 1) / kCellsPerWave;
   return (int64_t)D * n_iso * nchunk;
 }
 
@@ -301,7 +329,8 @@ hipError_t launch_contour(const ContourArgs& a, hipStream_t s) {
   p.W = a.W;
   p.H = a.H;
   p.cells = (int64_t)(a.W - 1) * (a.H - 1);
-  p.nchunk = (p.cells + kCellsPerBlock - 1) / kCellsPerBlock;
+  p.nchunk = (p.cells + kCellsPerWave - 1) / kCellsPerWave;
+  p.bpf = (p.nchunk + kWavesPerBlock - 1) / kWavesPerBlock;
   p.cases = a.cases;
   p.counts = a.counts;
   p.offsets = a.offsets;
@@ -310,16 +339,17 @@ hipError_t launch_contour(const ContourArgs& a, hipStream_t s) {
   p.ids = a.ids;
   p.capacity = a.capacity;
   p.g = GridD{a.x0, a.y0, a.dx, a.dy};
-  const int64_t blocks = (int64_t)a.D * p.nchunk;
-  const int64_t entries = blocks * a.n_iso;
+  const int64_t blocks = (int64_t)a.D * p.bpf;
+  const int64_t entries = (int64_t)a.D * p.nchunk * a.n_iso;
   const int64_t tiles = contour_scan_tiles(entries);
-  hipLaunchKernelGGL(contour_count_kernel, dim3((unsigned)blocks), dim3(kCellsPerBlock), 0, s, p);
+  hipLaunchKernelGGL(contour_count_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                     s, p);
   hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, a.counts,
                      a.offsets, a.tile_sums, entries);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, a.tile_sums, tiles, a.total);
   if (a.capacity > 0)
-    hipLaunchKernelGGL(contour_emit_kernel, dim3((unsigned)blocks), dim3(kCellsPerBlock), 0, s,
-                       p);
+    hipLaunchKernelGGL(contour_emit_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                       s, p);
   return hipGetLastError();
 }
 

@@ -144,10 +144,11 @@ struct ContourArgs {
   float* segs;           // [capacity][4]
   int32_t* ids;          // [capacity][3] or null
   int64_t capacity;
-  // scratch (library-owned): contour_scratch_entries() int32 counts and
-  // int64 offsets, contour_scan_tiles() int64 tile sums, one int64 total
+  // scratch (library-owned): contour_scratch_entries() int32 counts, which
+  // the scan turns into int32 offsets in place; contour_scan_tiles() int64
+  // tile sums; one int64 total
   int32_t* counts;
-  int64_t* offsets;
+  int32_t* offsets;
   int64_t* tile_sums;
   int64_t* total;
 };
