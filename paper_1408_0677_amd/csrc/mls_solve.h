@@ -54,7 +54,7 @@ __device__ __forceinline__ double shift_entry(int r, int c, double ex, double ey
 // divides the weight sum before the floor test (weights that were scaled
 // by a common factor).
 template <int DEG, typename Acc>
-__device__ uint8_t solve_node(const Acc* g, int D, double ex, double ey,
+__device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, double ey,
                               double tau, double floor_w, float* fields,
                               int64_t plane, const float* shift = nullptr,
                               const float* scale = nullptr, double wscale = 1.0) {
