@@ -66,24 +66,28 @@ __device__ __forceinline__ int cell_case(const Corners& c, float iso) {
          (c.v3 >= iso ? 8 : 0);
 }
 
-// Fills seg[][2] with (from, to) edges; returns the segment count.
-__device__ __forceinline__ int case_segments(int cs, const Corners& c, float iso, int seg[2][2]) {
+// (from, to) edges of the case's segments in (a0, a1) and (b0, b1);
+// returns the segment count.  Scalars, not an array, so that nothing of a
+// cell's state needs addressable (scratch) storage.
+__device__ __forceinline__ int case_segments(int cs, const Corners& c, float iso, int& a0,
+                                             int& a1, int& b0, int& b1) {
 #pragma clang fp contract(off)
+  a0 = a1 = b0 = b1 = 0;
   if (cs == 5 || cs == 10) {
     const float centre = ((c.v0 + c.v1) + (c.v2 + c.v3)) * 0.25f;
     const bool joined = centre >= iso;
     if (cs == 5) {
-      seg[0][0] = 0; seg[0][1] = joined ? 1 : 3;
-      seg[1][0] = 2; seg[1][1] = joined ? 3 : 1;
+      a0 = 0; a1 = joined ? 1 : 3;
+      b0 = 2; b1 = joined ? 3 : 1;
     } else {
-      seg[0][0] = joined ? 3 : 1; seg[0][1] = 0;
-      seg[1][0] = joined ? 1 : 3; seg[1][1] = 2;
+      a0 = joined ? 3 : 1; a1 = 0;
+      b0 = joined ? 1 : 3; b1 = 2;
     }
     return 2;
   }
   if (cs == 255 || kOneSegment[cs][0] < 0) return 0;
-  seg[0][0] = kOneSegment[cs][0];
-  seg[0][1] = kOneSegment[cs][1];
+  a0 = kOneSegment[cs][0];
+  a1 = kOneSegment[cs][1];
   return 1;
 }
 
@@ -135,6 +139,16 @@ struct ContourParams {
   GridD g;
 };
 
+// Workgroups are dispatched round-robin over the eight XCDs (block b runs on
+// XCD b % 8), each with its own L2.  Renumbering so that every XCD works
+// through one contiguous eighth of the logical blocks keeps the chunk that
+// reads rows i and i + 1 on the XCD that read row i a few blocks earlier,
+// so the second read of a row hits that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t per = n / 8, rem = n % 8, x = b % 8, i = b / 8;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // The cells of one wave chunk: corners in registers, and the range of the
 // lane's valid corners (an isovalue outside it crosses none of them).
 struct WaveCells {
@@ -171,8 +185,9 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
 
 __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(ContourParams p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int d = (int)(blockIdx.x / p.bpf);
-  const int64_t chunk = (blockIdx.x % p.bpf) * kWavesPerBlock + wave;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int d = (int)(blk / p.bpf);
+  const int64_t chunk = (blk % p.bpf) * kWavesPerBlock + wave;
   if (chunk >= p.nchunk) return;   // whole wave; the kernel has no barrier
   const float* f = p.fields + (int64_t)d * p.W * p.H;
   WaveCells w;
@@ -273,8 +288,9 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t* sums, int64_t 
 
 __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(ContourParams p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int d = (int)(blockIdx.x / p.bpf);
-  const int64_t chunk = (blockIdx.x % p.bpf) * kWavesPerBlock + wave;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int d = (int)(blk / p.bpf);
+  const int64_t chunk = (blk % p.bpf) * kWavesPerBlock + wave;
   if (chunk >= p.nchunk) return;
   const float* f = p.fields + (int64_t)d * p.W * p.H;
   WaveCells w;
@@ -287,23 +303,27 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(Conto
     int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
 #pragma unroll
     for (int q = 0; q < kCellsPerLane; ++q) {
-      const int cs = w.in[q] ? cell_case(w.c[q], iso) : 255;
-      int seg[2][2];
-      const int ns = w.in[q] ? case_segments(cs, w.c[q], iso, seg) : 0;
+      const Corners cq = w.c[q];
+      const int iq = w.i[q], jq = w.j[q];
+      const int cs = w.in[q] ? cell_case(cq, iso) : 255;
+      int a0, a1, b0, b1;
+      const int ns = w.in[q] ? case_segments(cs, cq, iso, a0, a1, b0, b1) : 0;
       const uint64_t one = __ballot(ns >= 1), two = __ballot(ns == 2);
       const int64_t base = run + __popcll(one & below) + __popcll(two & below);
       run += __popcll(one) + __popcll(two);
-      for (int s2 = 0; s2 < ns; ++s2) {
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
         const int64_t o = base + s2;
-        if (o >= p.capacity) break;
-        float x0, y0, x1, y1;
-        edge_point(seg[s2][0], w.c[q], iso, w.i[q], w.j[q], p.g, &x0, &y0);
-        edge_point(seg[s2][1], w.c[q], iso, w.i[q], w.j[q], p.g, &x1, &y1);
-        reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
-        if (p.ids) {
-          p.ids[3 * o] = d;
-          p.ids[3 * o + 1] = k;
-          p.ids[3 * o + 2] = (int32_t)w.cell[q];
+        if (s2 < ns && o < p.capacity) {
+          float x0, y0, x1, y1;
+          edge_point(s2 ? b0 : a0, cq, iso, iq, jq, p.g, &x0, &y0);
+          edge_point(s2 ? b1 : a1, cq, iso, iq, jq, p.g, &x1, &y1);
+          reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
+          if (p.ids) {
+            p.ids[3 * o] = d;
+            p.ids[3 * o + 1] = k;
+            p.ids[3 * o + 2] = (int32_t)w.cell[q];
+          }
         }
       }
     }
