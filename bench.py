@@ -128,8 +128,9 @@ LP_SOURCES = ["paper_1408_0677_amd/csrc/mls_fit_lp.hip", "paper_1408_0677_amd/cs
 
 def serve_bench(args):
     """The served form on the request mix: closed-loop saturation for the
-    16-bit served precision and the plain path, then Poisson arrivals at
-    0.5, 0.8 and 1.0 times the saturation rate."""
+    16-bit served precision (with the library plan, then with the autotuner
+    choosing slab widths per shape class) and the plain path, then Poisson
+    arrivals at 0.5, 0.8 and 1.0 times the saturation rate."""
     import torch
     from paper_1408_0677_amd import api, workloads as wl
 
@@ -174,8 +175,13 @@ def serve_bench(args):
            "config": {"workload": "c4_256_requests_mixed", "requests": len(reqs),
                       "slots": args.slots, "budget_bytes": budget,
                       "pairs_total": int(sum(pairs))}}
-    for prec in ("fp16", "f64"):
-        run(prec)                                  # warm-up pass
+    n_classes = 0
+    for label, prec, tune in (("fp16", "fp16", False), ("fp16_tuned", "fp16", True),
+                              ("f64", "f64", False)):
+        srv.tuning(tune)
+        run(prec)                                  # warm-up pass (tunes new shape classes)
+        if tune:
+            n_classes = srv.tuned_classes()
         wall, lat = run(prec)
         rate = len(reqs) / wall
         rec = {"saturation_requests_per_s": rate, "pairs_per_s": sum(pairs) / wall,
@@ -188,8 +194,9 @@ def serve_bench(args):
                                       "achieved_requests_per_s": len(reqs) / wall2,
                                       "p50_ms": 1e3 * float(np.percentile(lat2, 50)),
                                       "p99_ms": 1e3 * float(np.percentile(lat2, 99))}
-        out[prec] = rec
-    out["value"] = out["fp16"]["saturation_requests_per_s"]
+        out[label] = rec
+    out["tuned_shape_classes"] = n_classes
+    out["value"] = out["fp16_tuned"]["saturation_requests_per_s"]
     srv.close()
     return out
 

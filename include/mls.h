@@ -111,6 +111,10 @@ typedef struct {
   int32_t lp_terms;     /* 16-bit terms per feature for MLS_PREC_BF16/FP16:
                            1, 2 or 3; 0 selects the default (3 for
                            bfloat16, 2 for float16) */
+  int32_t lp_slab;      /* MLS_PREC_BF16/FP16: attributes per workgroup
+                           slab, 0 = the library's plan, else 1 ..
+                           MLS_LP_MAX_SLAB_<basis>.  A tuning knob only:
+                           results are bitwise the same for every value */
 } mls_solve_opts;
 
 typedef struct mls_context mls_context;
@@ -131,6 +135,9 @@ typedef struct mls_context mls_context;
  * / h, per basis (the constant basis has no limit).  The tile shares one
  * moment frame; moving the float32 moments to a node that far from it
  * cancels digits (the quadratic basis more, through fourth powers). */
+#define MLS_LP_MAX_SLAB_CONSTANT 40
+#define MLS_LP_MAX_SLAB_LINEAR 40
+#define MLS_LP_MAX_SLAB_QUADRATIC 18
 #define MLS_LP_MAX_TILE_SPAN_LINEAR 4.0
 #define MLS_LP_MAX_TILE_SPAN_QUADRATIC 2.5
 
@@ -284,6 +291,21 @@ mls_status mls_server_poll(mls_server* srv, uint64_t ticket, mls_result* out);
 mls_status mls_server_wait(mls_server* srv, uint64_t ticket, mls_result* out);
 /* Detail of the calling thread's last failed server call. */
 const char* mls_server_last_error(void);
+
+/*
+ * Autotuner of the served 16-bit fits (callers that serve many requests of
+ * recurring shapes).  enable = 1: the first request of each shape class
+ * (precision, basis, weight, D, and the node-tile and point counts to the
+ * nearest power of two below) is run once per candidate slab width on its
+ * slot and timed; the fastest width serves the class from then on.
+ * Requests that set opts.lp_slab themselves are not tuned.  cache_path
+ * (may be NULL): a text file of "class = width" lines, read now and
+ * rewritten whenever a class is added.  Tuning never changes a result bit.
+ */
+mls_status mls_server_tuning(mls_server* srv, int32_t enable, const char* cache_path);
+
+/* Number of shape classes the tuner holds. */
+int64_t mls_server_tuned_classes(mls_server* srv);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,8 @@ EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_context_destroy", "mls_fit", "mls_contour", "mls_fit_scratch_bytes",
            "mls_context_reserve", "mls_server_create", "mls_server_destroy",
            "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
-           "mls_server_poll", "mls_server_wait", "mls_server_last_error")
+           "mls_server_poll", "mls_server_wait", "mls_server_last_error",
+           "mls_server_tuning", "mls_server_tuned_classes")
 
 
 class MlsGrid(ctypes.Structure):
@@ -34,7 +35,7 @@ class MlsWeight(ctypes.Structure):
 
 class MlsSolveOpts(ctypes.Structure):
     _fields_ = [("pivot_tol", ctypes.c_double), ("weight_floor", ctypes.c_double),
-                ("lp_terms", ctypes.c_int32)]
+                ("lp_terms", ctypes.c_int32), ("lp_slab", ctypes.c_int32)]
 
 
 class MlsRequest(ctypes.Structure):
@@ -102,5 +103,9 @@ def load():
     lib.mls_server_wait.restype = ctypes.c_int
     lib.mls_server_last_error.argtypes = []
     lib.mls_server_last_error.restype = ctypes.c_char_p
+    lib.mls_server_tuning.argtypes = [P, i32, ctypes.c_char_p]
+    lib.mls_server_tuning.restype = ctypes.c_int
+    lib.mls_server_tuned_classes.argtypes = [P]
+    lib.mls_server_tuned_classes.restype = ctypes.c_int64
     _lib = lib
     return lib

@@ -88,7 +88,7 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
         h: float = 0.05, alpha: float = 1.0, precision: str = "f64",
         pivot_tol: float = 1e-8, weight_floor: float = 1e-6, lp_terms: int = 0, out=None,
         degree_out=None, want_degree: bool = True, ctx: Context | None = None,
-        stream=None):
+        stream=None, lp_slab: int = 0):
     """MLS fields of ``values`` (N, D) at the nodes of ``grid``.
 
     ``points`` float32 (N, 2) and ``values`` float32 (N, D) are contiguous
@@ -109,7 +109,8 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
     ctx = ctx or default_context(points.device.index)
     g = grid_struct(grid)
     wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
-    opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor), int(lp_terms))
+    opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor), int(lp_terms),
+                             int(lp_slab))
     st = _lib.load().mls_fit(ctx.handle, _ptr(points), _ptr(values), n, d, BASIS[basis],
                              ctypes.byref(wt), ctypes.byref(g), PRECISION[precision],
                              ctypes.byref(opts), _ptr(out), _ptr(degree_out),
@@ -188,13 +189,26 @@ class Server:
     requests must stay alive until their result is collected."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 2 << 30, slots: int = 4,
-                 slot_scratch: int = 64 << 20):
+                 slot_scratch: int = 64 << 20, tune: bool = False,
+                 tuner_cache: str | None = None):
         self._ptr = ctypes.c_void_p()
         st = _lib.load().mls_server_create(int(device), int(hbm_budget), int(slots),
                                            int(slot_scratch), ctypes.byref(self._ptr))
         if st != STATUS_OK:
             raise ServerError(st, "mls_server_create")
         self._keep = {}
+        if tune or tuner_cache:
+            self.tuning(tune, tuner_cache)
+
+    def tuning(self, enable: bool, cache_path: str | None = None):
+        st = _lib.load().mls_server_tuning(self._ptr, 1 if enable else 0,
+                                           None if cache_path is None else
+                                           str(cache_path).encode())
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_tuning")
+
+    def tuned_classes(self) -> int:
+        return int(_lib.load().mls_server_tuned_classes(self._ptr))
 
     def close(self):
         if self._ptr:
@@ -227,12 +241,12 @@ class Server:
     def submit(self, pointset: int, grid: dict, out, degree_out=None, basis: str = "linear",
                weight: str = "gaussian", h: float = 0.05, alpha: float = 1.0,
                precision: str = "f64", pivot_tol: float = 1e-8, weight_floor: float = 1e-6,
-               lp_terms: int = 0) -> int:
+               lp_terms: int = 0, lp_slab: int = 0) -> int:
         req = _lib.MlsRequest(int(pointset), BASIS[basis],
                               _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha)),
                               grid_struct(grid), PRECISION[precision],
                               _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor),
-                                                int(lp_terms)),
+                                                int(lp_terms), int(lp_slab)),
                               out.data_ptr(),
                               None if degree_out is None else degree_out.data_ptr())
         t = ctypes.c_uint64()

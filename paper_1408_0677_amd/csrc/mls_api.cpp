@@ -246,12 +246,20 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
     return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
   double tau = 1e-8, floor_w = 1e-6;
   int terms = precision == MLS_PREC_FP16 ? 2 : 3;
+  int slab = 0;
   if (opts) {
     tau = opts->pivot_tol;
     floor_w = opts->weight_floor;
     if (opts->lp_terms < 0 || opts->lp_terms > 3)
       return fail(MLS_ERR_INVALID_ARG, "lp_terms = %d; need 0..3", opts->lp_terms);
     if (opts->lp_terms > 0) terms = opts->lp_terms;
+    const int max_slab = basis == MLS_BASIS_QUADRATIC ? MLS_LP_MAX_SLAB_QUADRATIC
+                         : basis == MLS_BASIS_LINEAR  ? MLS_LP_MAX_SLAB_LINEAR
+                                                      : MLS_LP_MAX_SLAB_CONSTANT;
+    if (opts->lp_slab < 0 || opts->lp_slab > max_slab)
+      return fail(MLS_ERR_INVALID_ARG, "lp_slab = %d; need 0..%d for this basis", opts->lp_slab,
+                  max_slab);
+    slab = opts->lp_slab;
     if (!is_finite(tau) || !(tau > 0.0) || !(tau <= 1.0))
       return fail(MLS_ERR_INVALID_ARG, "pivot_tol = %g; need 0 < tau <= 1", tau);
     if (!is_finite(floor_w) || floor_w < 0.0)
@@ -292,6 +300,7 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   a.H = grid->height;
   a.tau = tau;
   a.floor_w = floor_w;
+  a.lp_slab = slab;
   a.fields = d_fields;
   a.deg_out = d_degree;
   hipStream_t s = (hipStream_t)stream;

@@ -49,6 +49,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "../../include/mls.h"
 #include "mls_internal.h"
 #include "mls_solve.h"
 
@@ -571,8 +572,29 @@ hipError_t launch_lp_terms(const LPParams& p, int deg, int nts, int terms, hipSt
 
 // Slab plan: feature tiles per slab (1..8) and attributes per slab (at most
 // kDsCap) that cover D with the fewest padded columns in total.
-void lp_slab_plan(int degree, int D, int* nts_out, int* ds_out, int* nslab_out) {
+static_assert((8 * 16 - 1) / 1 >= MLS_LP_MAX_SLAB_CONSTANT && kDsCap == MLS_LP_MAX_SLAB_CONSTANT,
+              "constant-basis slab limit");
+static_assert((8 * 16 - 6) / 3 >= MLS_LP_MAX_SLAB_LINEAR && kDsCap == MLS_LP_MAX_SLAB_LINEAR,
+              "linear-basis slab limit");
+static_assert((8 * 16 - 15) / 6 == MLS_LP_MAX_SLAB_QUADRATIC, "quadratic-basis slab limit");
+
+int lp_max_slab(int degree) {
   const int m = basis_terms(degree), nmom = moment_terms(degree);
+  const int ds = (8 * 16 - nmom) / m;
+  return ds < kDsCap ? ds : kDsCap;
+}
+
+void lp_slab_plan(int degree, int D, int forced_ds, int* nts_out, int* ds_out, int* nslab_out) {
+  const int m = basis_terms(degree), nmom = moment_terms(degree);
+  if (forced_ds > 0) {
+    const int ds = forced_ds < D ? forced_ds : D;
+    int nts = 1;
+    while (nts * 16 < nmom + m * ds) ++nts;
+    *nts_out = nts;
+    *ds_out = ds;
+    *nslab_out = (D + ds - 1) / ds;
+    return;
+  }
   int best_cost = 1 << 30, best_nts = 8, best_ds = 1, best_ns = D;
   for (int nts = 1; nts <= 8; ++nts) {
     int ds = (nts * 16 - nmom) / m;
@@ -606,7 +628,7 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
                          const float* scale, bool fp16, int terms, const LPCells* cells,
                          hipStream_t stream) {
   int nts, ds, nslab;
-  lp_slab_plan(a.degree, a.D, &nts, &ds, &nslab);
+  lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
   LPParams p;
   p.pts = a.pts;
   p.vals_t = vals_t;

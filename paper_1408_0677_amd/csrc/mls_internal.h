@@ -21,6 +21,7 @@ struct FitArgs {
   double tau, floor_w;
   float* fields;        // [D][H][W]
   uint8_t* deg_out;     // [H][W] or null
+  int32_t lp_slab;      // 16-bit paths: attributes per slab, 0 = lp_slab_plan's choice
 };
 
 // Number of basis terms m and of distinct moment monomials for a degree.
@@ -40,7 +41,11 @@ struct LPCells;
 hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shift,
                          const float* scale, bool fp16, int terms, const LPCells* cells,
                          hipStream_t stream);
-void lp_slab_plan(int degree, int D, int* nts, int* ds, int* nslab);
+// Attribute slabs of the 16-bit kernel: `forced_ds` attributes per slab
+// (0 = the cost model's choice); NTS feature tiles of 16 per slab.
+void lp_slab_plan(int degree, int D, int forced_ds, int* nts, int* ds, int* nslab);
+// Largest attributes per slab the kernel supports for a degree.
+int lp_max_slab(int degree);
 // Largest node offset across a 16 x 16 node tile, in units of h.
 double lp_tile_extent(double dx, double dy, double h);
 

@@ -20,6 +20,16 @@
 //     the slot's stream; it stamps the end time and frees the slot.
 //   - A request that fails validation fails alone at submit; one that can
 //     never fit the budget is rejected with MLS_ERR_OVER_BUDGET.
+//   - Autotuner (optional, mls_server_tuning): the 16-bit kernels take a
+//     slab width (attributes per workgroup, which sets the workgroup's
+//     feature-tile count).  The best width depends on the request's shape
+//     (basis, D, grid size, N) through occupancy, the number of workgroups
+//     and the moment columns every slab repeats.  The first request of a
+//     shape class is run once per candidate width on its own slot, timed
+//     with stream events, and the fastest width is kept for the class (and
+//     written to a cache file if one was given); later requests of the
+//     class use it.  The width changes no result bit, so tuning is
+//     invisible in the output.
 // Results of a request do not depend on what else runs: each fit is
 // deterministic and touches only its own slot's scratch.
 #include <hip/hip_runtime.h>
@@ -30,9 +40,12 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <deque>
 #include <map>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -66,6 +79,7 @@ struct Ticket {
 
 struct Slot {
   hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // tuner timing
   mls_context* ctx = nullptr;
   Ticket* running = nullptr;
   std::atomic<bool> finished{false};  // set by the stream's host function
@@ -79,8 +93,16 @@ struct Completion {
 
 }  // namespace
 
+// Shape classes and their tuned slab widths.
+struct Tuner {
+  bool on = false;
+  std::string path;                 // cache file, or empty
+  std::map<std::string, int> table; // class key -> attributes per slab
+};
+
 struct mls_server {
   int device = 0;
+  Tuner tuner;
   size_t budget = 0;
   size_t slot_scratch = 0;
   size_t points_bytes = 0;
@@ -152,13 +174,109 @@ bool retire_finished(mls_server* s) {
   return any;
 }
 
-// Launch a ticket on a free slot.  Called with the lock held.
-void launch(mls_server* s, int si, Ticket* t) {
+int ilog2(int64_t v) {
+  int k = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++k;
+  }
+  return k;
+}
+
+// Shape class of a 16-bit request: precision, basis, weight, D, and the
+// node-tile and point counts to the nearest power of two below.
+std::string tune_key(const mls_request& r, const PointSet& ps) {
+  const int64_t tiles = (int64_t)((r.grid.width + 15) / 16) * ((r.grid.height + 15) / 16);
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "p%d b%d w%d d%d t%d n%d", r.precision, r.basis,
+                r.weight.kind, ps.d, ilog2(tiles), ilog2(ps.n));
+  return buf;
+}
+
+// Candidate slab widths: the widest slab for each feature-tile count, the
+// four cheapest by the tile-count model (slabs x tiles per slab).
+std::vector<int> slab_candidates(int basis, int D) {
+  const int m = mls::basis_terms(basis), nmom = mls::moment_terms(basis);
+  const int cap = basis == MLS_BASIS_QUADRATIC ? MLS_LP_MAX_SLAB_QUADRATIC
+                  : basis == MLS_BASIS_LINEAR  ? MLS_LP_MAX_SLAB_LINEAR
+                                               : MLS_LP_MAX_SLAB_CONSTANT;
+  std::vector<std::pair<int, int>> c;   // (cost, ds)
+  for (int nts = 1; nts <= 8; ++nts) {
+    int ds = (16 * nts - nmom) / m;
+    ds = std::min(std::min(ds, cap), D);
+    if (ds < 1) continue;
+    bool seen = false;
+    for (auto& e : c) seen |= e.second == ds;
+    if (seen) continue;
+    int need = 1;
+    while (need * 16 < nmom + m * ds) ++need;
+    c.push_back({((D + ds - 1) / ds) * need, ds});
+  }
+  std::sort(c.begin(), c.end());
+  std::vector<int> out;
+  for (size_t i = 0; i < c.size() && i < 4; ++i) out.push_back(c[i].second);
+  return out;
+}
+
+void save_tuner(const mls_server* s) {
+  if (s->tuner.path.empty()) return;
+  FILE* f = std::fopen(s->tuner.path.c_str(), "w");
+  if (!f) return;
+  for (auto& kv : s->tuner.table) std::fprintf(f, "%s = %d\n", kv.first.c_str(), kv.second);
+  std::fclose(f);
+}
+
+// Time every candidate slab width on the request itself (each run writes
+// the same outputs) and return the fastest.  Runs unlocked: the slot is
+// already marked busy with this ticket and its point set is pinned by the
+// ticket's use count.
+int tune_request(Slot& sl, const mls_request& r, const PointSet& ps,
+                 std::unique_lock<std::mutex>& lk) {
+  const std::vector<int> cands = slab_candidates(r.basis, ps.d);
+  if (cands.size() < 2) return cands.empty() ? 0 : cands[0];
+  lk.unlock();
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int c : cands) {
+    mls_solve_opts o = r.opts;
+    o.lp_slab = c;
+    float ms = 0.0f;
+    bool ok = true;
+    for (int rep = 0; rep < 2 && ok; ++rep) {   // the first run loads the kernel
+      ok = hipEventRecord(sl.ev0, sl.stream) == hipSuccess;
+      ok = ok && mls_fit(sl.ctx, ps.pts, ps.vals, ps.n, ps.d, r.basis, &r.weight, &r.grid,
+                         r.precision, &o, r.d_fields, r.d_degree, (void*)sl.stream) == MLS_OK;
+      ok = ok && hipEventRecord(sl.ev1, sl.stream) == hipSuccess;
+      ok = ok && hipEventSynchronize(sl.ev1) == hipSuccess;
+      ok = ok && hipEventElapsedTime(&ms, sl.ev0, sl.ev1) == hipSuccess;
+    }
+    if (ok && (best == 0 || ms < best_ms)) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  lk.lock();
+  return best;
+}
+
+// Launch a ticket on a free slot.  Called with the lock held (released
+// while a new shape class is tuned).
+void launch(mls_server* s, int si, Ticket* t, std::unique_lock<std::mutex>& lk) {
   Slot& sl = s->slots[si];
   PointSet& ps = s->psets[t->req.pointset];
   t->res.t_admit = seconds_since(s);
   sl.running = t;
-  const mls_request& r = t->req;
+  mls_request& r = t->req;
+  if (s->tuner.on && r.precision != MLS_PREC_F64 && r.opts.lp_slab == 0) {
+    const std::string key = tune_key(r, ps);
+    auto it = s->tuner.table.find(key);
+    if (it == s->tuner.table.end()) {
+      const int best = tune_request(sl, r, ps, lk);
+      it = s->tuner.table.emplace(key, best).first;
+      save_tuner(s);
+    }
+    r.opts.lp_slab = it->second;
+  }
   mls_status st = mls_fit(sl.ctx, ps.pts, ps.vals, ps.n, ps.d, r.basis, &r.weight, &r.grid,
                           r.precision, &r.opts, r.d_fields, r.d_degree, (void*)sl.stream);
   t->res.t_start = seconds_since(s);
@@ -216,7 +334,7 @@ void scheduler(mls_server* s) {
       if (s->slots[si].running) continue;
       Ticket* t = s->queue.front();
       s->queue.pop_front();
-      launch(s, si, t);
+      launch(s, si, t, lk);
     }
     // released point sets with no users left
     for (auto it = s->psets.begin(); it != s->psets.end();) {
@@ -262,6 +380,8 @@ mls_status mls_server_create(int32_t device, size_t hbm_budget_bytes, int32_t sl
   auto cleanup = [&]() {
     for (int j = 0; j < slots; ++j) {
       if (s->slots[j].ctx) mls_context_destroy(s->slots[j].ctx);
+      if (s->slots[j].ev0) (void)hipEventDestroy(s->slots[j].ev0);
+      if (s->slots[j].ev1) (void)hipEventDestroy(s->slots[j].ev1);
       if (s->slots[j].stream) (void)hipStreamDestroy(s->slots[j].stream);
     }
   };
@@ -278,9 +398,11 @@ mls_status mls_server_create(int32_t device, size_t hbm_budget_bytes, int32_t sl
       return st;
     }
     hipError_t e = hipStreamCreateWithFlags(&s->slots[i].stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&s->slots[i].ev0);
+    if (e == hipSuccess) e = hipEventCreate(&s->slots[i].ev1);
     if (e != hipSuccess) {
       cleanup();
-      return sfail(MLS_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+      return sfail(MLS_ERR_DEVICE, "stream or event creation: %s", hipGetErrorString(e));
     }
   }
   mls_server* raw = s.release();
@@ -304,6 +426,8 @@ void mls_server_destroy(mls_server* s) {
       (void)hipStreamSynchronize(sl.stream);
       (void)hipStreamDestroy(sl.stream);
     }
+    if (sl.ev0) (void)hipEventDestroy(sl.ev0);
+    if (sl.ev1) (void)hipEventDestroy(sl.ev1);
     if (sl.ctx) mls_context_destroy(sl.ctx);
   }
   for (auto& kv : s->psets) {
@@ -311,6 +435,36 @@ void mls_server_destroy(mls_server* s) {
     (void)hipFree(kv.second.vals);
   }
   delete s;
+}
+
+mls_status mls_server_tuning(mls_server* s, int32_t enable, const char* cache_path) {
+  g_srv_error[0] = '\0';
+  if (!s) return sfail(MLS_ERR_INVALID_ARG, "server is NULL");
+  if (enable != 0 && enable != 1) return sfail(MLS_ERR_INVALID_ARG, "enable = %d", enable);
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->tuner.on = enable == 1;
+  s->tuner.path = cache_path ? cache_path : "";
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[160];
+      while (std::fgets(line, sizeof(line), f)) {
+        char* eq = std::strrchr(line, '=');
+        if (!eq) continue;
+        const int ds = std::atoi(eq + 1);
+        std::string key(line, eq - line);
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        if (ds >= 1 && ds <= MLS_LP_MAX_SLAB_LINEAR && !key.empty()) s->tuner.table[key] = ds;
+      }
+      std::fclose(f);
+    }
+  }
+  return MLS_OK;
+}
+
+int64_t mls_server_tuned_classes(mls_server* s) {
+  if (!s) return 0;
+  std::lock_guard<std::mutex> lk(s->mu);
+  return (int64_t)s->tuner.table.size();
 }
 
 mls_status mls_server_put_points(mls_server* s, const float* d_points, const float* d_values,

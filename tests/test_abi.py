@@ -71,6 +71,9 @@ def _fit(lib, n=10, d=2, basis=1, kind=0, h=0.1, alpha=1.0, grid=(0.0, 0.0, 0.1,
     (dict(opts=(0.0, 1e-6, 0)), b"pivot_tol"),
     (dict(opts=(1e-8, -1.0, 0)), b"weight_floor"),
     (dict(opts=(1e-8, 1e-6, 4)), b"lp_terms"),
+    (dict(opts=(1e-8, 1e-6, 0, -1)), b"lp_slab"),
+    (dict(basis=2, opts=(1e-8, 1e-6, 0, 19)), b"lp_slab"),
+    (dict(basis=1, opts=(1e-8, 1e-6, 0, 41)), b"lp_slab"),
     (dict(pts=0), b"d_points is NULL"),
     (dict(vals=0), b"d_values is NULL"),
     (dict(fields=0), b"d_fields is NULL"),
@@ -147,5 +150,7 @@ def test_server_arguments_rejected_without_device(lib):
     assert lib.mls_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == -1
     res = _lib.MlsResult()
     assert lib.mls_server_poll(None, 1, ctypes.byref(res)) == -1
+    assert lib.mls_server_tuning(None, 1, None) == -1
+    assert lib.mls_server_tuned_classes(None) == 0
     assert lib.mls_status_string(-5) == b"MLS_ERR_OVER_BUDGET"
     assert lib.mls_status_string(1) == b"MLS_PENDING"

@@ -274,3 +274,30 @@ def test_c5_full_size_sampled(torch_dev, oracle):
                  dmin_pass=1e-2)
     note("per-field max " + " ".join(f"{v:.1e}" for v in st["per_field_max_pass"]))
     check_lp(st, "bf16", 3)
+
+
+@pytest.mark.parametrize("case", [
+    # basis, precision, weight, D, slab widths
+    ("quadratic", "bf16", "gaussian", 32, (5, 8, 13, 16, 18)),
+    ("linear", "fp16", "gaussian", 45, (3, 8, 26, 40)),
+    ("quadratic", "bf16", "wendland", 7, (1, 2, 5)),
+])
+def test_slab_width_bitwise_invariant(torch_dev, case):
+    """The slab width (attributes per workgroup) is a tuning knob: every
+    width gives the same bits (each output column of the contraction is
+    summed the same way whatever shares its workgroup)."""
+    from paper_1408_0677_amd import workloads as wl
+    basis, prec, weight, D, widths = case
+    note(f"case slab invariance {basis} {prec} {weight} D={D}")
+    rng = np.random.default_rng(D)
+    pts = rng.random((3000, 2))
+    vals = wl.smooth_fields(rng, pts, D)
+    grid = wl.pixel_grid(96, 80)
+    h = 0.08 if weight == "gaussian" else 0.09
+    ref, dref = gpu_fit(torch_dev, pts, vals, grid, basis=basis, weight=weight, h=h,
+                        precision=prec)
+    for ds in widths:
+        f, dg = gpu_fit(torch_dev, pts, vals, grid, basis=basis, weight=weight, h=h,
+                        precision=prec, lp_slab=ds)
+        assert np.array_equal(dg, dref), ds
+        assert np.array_equal(f.view(np.uint32), ref.view(np.uint32)), ds

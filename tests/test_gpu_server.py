@@ -144,3 +144,51 @@ def test_errors_are_isolated(torch_dev):
     with pytest.raises(api.ServerError):
         srv.submit(pid, grid, out)
     srv.close()
+
+
+def test_tuned_server_equals_direct(torch_dev, tmp_path):
+    """With the autotuner on, the first request of each shape class is timed
+    over candidate slab widths; every result still equals the direct fit
+    bit for bit, and the chosen widths persist in the cache file."""
+    import torch
+    from paper_1408_0677_amd import api, workloads as wl
+    note("case tuned server")
+    cache = tmp_path / "tuner.txt"
+    srv = api.Server(slots=3, hbm_budget=1 << 30, slot_scratch=64 << 20, tune=True,
+                     tuner_cache=str(cache))
+    rng = np.random.default_rng(5)
+    reqs = []
+    for q in range(8):
+        n = 3000
+        D = (24, 6)[q % 2]
+        basis = ("quadratic", "linear")[q % 2]
+        prec = ("bf16", "fp16")[(q // 2) % 2]
+        pts = rng.random((n, 2)).astype(np.float32)
+        vals = wl.smooth_fields(rng, pts, D).astype(np.float32)
+        reqs.append((pts, vals, basis, prec))
+    tickets, outs = [], []
+    grid = wl.pixel_grid(128, 96)
+    for pts, vals, basis, prec in reqs:
+        P = torch.from_numpy(pts).cuda()
+        V = torch.from_numpy(vals).cuda()
+        pid = srv.put_points(P, V)
+        out = torch.empty((V.shape[1], 96, 128), device="cuda")
+        deg = torch.empty((96, 128), dtype=torch.uint8, device="cuda")
+        tickets.append(srv.submit(pid, grid, out, deg, basis=basis, h=0.07, precision=prec))
+        outs.append((out, deg, P, V, basis, prec))
+    for t in tickets:
+        assert srv.wait(t)["status"] == 0
+    classes = srv.tuned_classes()
+    assert classes >= 2
+    for out, deg, P, V, basis, prec in outs:
+        f, d = api.fit(P, V, grid, basis=basis, h=0.07, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(d, deg)
+        assert torch.equal(f.view(torch.int32), out.view(torch.int32))
+    srv.close()
+    lines = [ln for ln in cache.read_text().splitlines() if "=" in ln]
+    assert len(lines) == classes
+    srv2 = api.Server(slots=1, hbm_budget=1 << 28, slot_scratch=16 << 20, tune=True,
+                      tuner_cache=str(cache))
+    assert srv2.tuned_classes() == classes
+    srv2.close()
