@@ -47,7 +47,22 @@ constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 constexpr int kCols = 16;      // node columns per tile (one M-tile)
 constexpr int KT = MLS_F64_KT; // points per LDS chunk
-constexpr int KS = KT + 4;     // LDS row stride in doubles (keeps 32B alignment)
+#ifndef MLS_F64_PAD
+#define MLS_F64_PAD 2
+#endif
+#ifndef MLS_F64_KG_UNROLL
+#define MLS_F64_KG_UNROLL 1
+#endif
+#ifndef MLS_F64_SETPRIO
+#define MLS_F64_SETPRIO 0
+#endif
+// LDS row stride in doubles.  A lane reads four consecutive doubles (two
+// 16-byte reads) of row i = lane % 16; with a stride of KT + 2 = 66
+// doubles (132 dwords, 4 mod 64) the sixteen rows of one read start in
+// sixteen different 4-bank groups, so the reads are free of bank
+// conflicts (a stride of 68 doubles puts rows i and i + 8 on the same
+// banks).
+constexpr int KS = KT + MLS_F64_PAD;
 // Waves that run the epilogue at the same time: the epilogue needs a
 // [nodes][features] float64 staging area per wave, and sharing it keeps the
 // kernel's LDS small enough for two workgroups per CU.
@@ -244,7 +259,8 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     // 3. MFMA sweep over the chunk
     const int i = lane & 15;        // A row (node column) / B column
     const int kq = (lane >> 4) * 4; // this lane's 4 points in each group of 16
-#pragma unroll 1
+    if (MLS_F64_SETPRIO) __builtin_amdgcn_s_setprio(1);
+#pragma unroll MLS_F64_KG_UNROLL
     for (int kg = 0; kg < KT; kg += 16) {
       const double* gxr = gx + i * KS + kg + kq;
       double ax[4] = {gxr[0], gxr[1], gxr[2], gxr[3]};
@@ -271,6 +287,7 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
         }
       }
     }
+    if (MLS_F64_SETPRIO) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
   }
 
