@@ -50,6 +50,7 @@ def cpu_baseline(w, row_stride=1, precision_note="FP64"):
     threads = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
     oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, weight=w.weight, h=w.h,
+                    alpha=w.alpha,
                     pixels=pix, threads=threads)
     dt = time.perf_counter() - t0
     if w.weight == "wendland":
@@ -208,11 +209,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "t1"],
                     help="c2: the 1024^2 float64 fit + contour step (default); c3: the "
                          "2048^2 / D = 64 quadratic bfloat16 fit; c5: the 4096^2 / "
                          "N = 10^6 Wendland bfloat16 fit + contour; c4: the served "
-                         "request mix with Poisson arrivals")
+                         "request mix with Poisson arrivals; t1: the paper's timing-table "
+                         "shape (600^2, N = 306 / 1000 / 2245, D = 2, linear, the "
+                         "inverse-distance weight of Eq. 4), float64")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -229,6 +232,23 @@ def main():
         print(json.dumps(serve_bench(args)), flush=True)
         return
 
+    if args.workload == "t1":
+        recs = [fit_step_bench(args, wl.t1(n), "f64") for n in (306, 1000, 2245)]
+        out = dict(recs[-1])
+        out["metric"] = ("MLS pixel·point pairs/s at the timing-table shape (600^2, D = 2, "
+                         "linear, inverse-distance weight)")
+        # the paper's Affine MLS timings at this shape (Table 1, GTX 285, its
+        # own shader): context for the same workload on other hardware
+        paper_s = {306: 0.026670, 1000: 0.100724, 2245: 0.242192}
+        out["per_n"] = [{"points": r["config"]["points"], "ms_per_step": r["ms_per_step"],
+                         "fit_p50_ms": r["latency_ms"]["fit_p50"], "pairs_per_s": r["value"],
+                         "paper_affine_s": paper_s[r["config"]["points"]],
+                         "speedup_vs_paper_fit": paper_s[r["config"]["points"]] * 1e3
+                                                 / r["latency_ms"]["fit_p50"],
+                         "cpu_baseline": r.get("cpu_baseline")} for r in recs]
+        out["vs_baseline"] = out["per_n"][-1]["speedup_vs_paper_fit"]
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "c2":
         w, prec = wl.c2(), "f64"
     elif args.workload == "c3":
@@ -254,7 +274,7 @@ def fit_step_bench(args, w, prec):
     degree = torch.empty((H, W), dtype=torch.uint8, device=dev)
     ctx = api.default_context(0)
     stream = torch.cuda.current_stream()
-    kw = dict(basis=w.basis, weight=w.weight, h=w.h, precision=prec, out=fields,
+    kw = dict(basis=w.basis, weight=w.weight, h=w.h, alpha=w.alpha, precision=prec, out=fields,
               degree_out=degree, ctx=ctx, stream=stream)
 
     # size the segment buffer once (outside the timed region)
@@ -364,7 +384,7 @@ def fit_step_bench(args, w, prec):
                      "kernel_ms": kern_ms},
     }
     if not args.no_cpu_baseline:
-        if args.workload == "c2":
+        if args.workload in ("c2", "t1"):
             out["cpu_baseline"] = cpu_baseline(w, row_stride=1)
         elif args.workload == "c3":
             out["cpu_baseline"] = cpu_baseline(w, row_stride=128)

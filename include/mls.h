@@ -171,9 +171,11 @@ void mls_context_destroy(mls_context* ctx);
  *  d_degree  uint8 [height][width] output (accepted degree, 255 for
  *            undetermined), device, or NULL
  * Supported in this build: the Gaussian weight with all three bases and all
- * precisions, the Wendland C2 weight with the 16-bit precisions (through a
- * device cell list); other combinations (the inverse-power weight, Wendland
- * with MLS_PREC_F64) return MLS_ERR_UNSUPPORTED.  The 16-bit precisions
+ * precisions; the Wendland C2 weight with the 16-bit precisions (through a
+ * device cell list); the inverse-distance weight with MLS_PREC_F64 on grids
+ * with nonzero dx and dy (a node that coincides exactly with data points
+ * takes the mean of their values, degree code 254; library scratch of about
+ * 16 n bytes).  Other combinations return MLS_ERR_UNSUPPORTED.  The 16-bit precisions
  * also return MLS_ERR_UNSUPPORTED when a node tile spans more than
  * MLS_LP_MAX_TILE_SPAN_<basis> (linear, quadratic), and MLS_PREC_FP16 when
  * tile-frame features would leave the float16 range; MLS_PREC_F64 serves

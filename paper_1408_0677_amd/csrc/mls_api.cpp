@@ -100,13 +100,24 @@ namespace mls {
 FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, double h,
                       double x0, double y0, double dx, double dy, int32_t W, int32_t H) {
   FitPlan p{};
-  if (precision == MLS_PREC_F64) return p;
   size_t off = 0;
   auto carve = [&](size_t bytes) {
     const size_t o = off;
     off += align_up(bytes, 256);
     return o;
   };
+  if (precision == MLS_PREC_F64) {
+    // the inverse-distance weight's exact-hit pass sorts (node, point) keys
+    if (wkind == MLS_W_INVPOW) {
+      p.o_keys = carve(4 * (size_t)n);
+      p.o_keys2 = carve(4 * (size_t)n);
+      p.o_perm = carve(4 * (size_t)n);
+      p.o_perm2 = carve(4 * (size_t)n);
+      p.o_hist = carve(4 * 256 * (size_t)radix_blocks(n));
+    }
+    p.total = off;
+    return p;
+  }
   const int64_t nblk = stage_partial_blocks(n);
   p.o_pmin = carve(sizeof(float) * (size_t)(nblk * d));
   p.o_pmax = carve(sizeof(float) * (size_t)(nblk * d));
@@ -269,10 +280,13 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   if (!d_values) return fail(MLS_ERR_INVALID_ARG, "d_values is NULL");
   if (!d_fields) return fail(MLS_ERR_INVALID_ARG, "d_fields is NULL");
   if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
-  if (weight->kind == MLS_W_INVPOW ||
+  if ((weight->kind == MLS_W_INVPOW && precision != MLS_PREC_F64) ||
       (weight->kind == MLS_W_WENDLAND_C2 && precision == MLS_PREC_F64))
     return fail(MLS_ERR_UNSUPPORTED, "weight kind %d is not available with precision %d",
                 weight->kind, precision);
+  if (weight->kind == MLS_W_INVPOW && (grid->dx == 0.0 || grid->dy == 0.0))
+    return fail(MLS_ERR_UNSUPPORTED, "the inverse-distance weight needs nonzero grid spacing "
+                "(nodes on one position would share their exact hits)");
 
   // ---- device ----
   hipError_t e = hipSetDevice(ctx->device);
@@ -305,8 +319,37 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   a.deg_out = d_degree;
   hipStream_t s = (hipStream_t)stream;
   if (precision == MLS_PREC_F64) {
+    mls::FitPlan plan{};
+    if (weight->kind == MLS_W_INVPOW) {
+      plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h, grid->x0, grid->y0,
+                                grid->dx, grid->dy, grid->width, grid->height);
+      if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
+    }
     e = mls::launch_fit_f64(a, s);
     if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+    if (weight->kind == MLS_W_INVPOW) {
+      char* base = (char*)ctx->fit_scratch.ptr;
+      mls::HitArgs hta;
+      hta.pts = d_points;
+      hta.vals = d_values;
+      hta.n = n;
+      hta.D = d;
+      hta.x0 = grid->x0;
+      hta.y0 = grid->y0;
+      hta.dx = grid->dx;
+      hta.dy = grid->dy;
+      hta.W = grid->width;
+      hta.H = grid->height;
+      hta.fields = d_fields;
+      hta.deg_out = d_degree;
+      hta.keys = (uint32_t*)(base + plan.o_keys);
+      hta.keys2 = (uint32_t*)(base + plan.o_keys2);
+      hta.idx = (uint32_t*)(base + plan.o_perm);
+      hta.idx2 = (uint32_t*)(base + plan.o_perm2);
+      hta.hist = (uint32_t*)(base + plan.o_hist);
+      e = mls::launch_hits(hta, s);
+      if (e != hipSuccess) return device_fail(e, "exact-hit pass launch");
+    }
     return MLS_OK;
   }
   const bool fp16 = precision == MLS_PREC_FP16;

@@ -74,6 +74,7 @@ struct F64Params {
   int64_t n;
   int D, F;
   double h, inv_h;
+  double alpha;        // inverse-distance exponent (INV kernels)
   double x0, y0, dx, dy;
   int W, H, tiles_x;
   double tau, floor_w;
@@ -109,7 +110,27 @@ template <int DEG, int R>
 __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
                                  int wave, int r0, int c0, int rows, int64_t plane);
 
-template <int DEG, int NT, int R>
+// Inverse-distance weight (Eq. 4) of a node-point offset (ox, oy) in units of
+// h: (ox^2 + oy^2)^(-alpha).  log2 of r^2 is taken as its binary exponent
+// plus the float32 log2 of its mantissa (so r^2 far outside float32's range
+// keeps an exact exponent), and the power is rebuilt as 2^frac scaled by
+// ldexp, so it cannot overflow float32 either; the relative error is that
+// of the float32 exp2/log2 (about 1e-7), a common factor of all features of
+// the pair.  Padding points carry an infinite offset and weigh 0.  A node on
+// a point (r^2 = 0) gets the clamp's large finite weight; such nodes are
+// overwritten by the exact-hit pass.
+__device__ __forceinline__ double invpow_weight(double ox, double oy, double alpha) {
+  const double r2 = ox * ox + oy * oy;
+  if (!(r2 < 1e300)) return 0.0;
+  int ex;
+  const double mant = frexp(fmax(r2, 1e-300), &ex);
+  const double l2 = (double)ex + (double)__log2f((float)mant);
+  const double e = fmin(-alpha * l2, 1000.0);
+  const double ip = floor(e);
+  return ldexp((double)exp2f((float)(e - ip)), (int)ip);
+}
+
+template <int DEG, int NT, int R, bool INV>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
   using L = F64Layout<DEG, NT, R>;
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
@@ -194,7 +215,13 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
       const double s = xaxis ? sx : sy;
       const double q = xaxis ? qx : qy;
       double* g = xaxis ? gx : gy;
-      if (k < kn) {
+      if (INV) {
+        // inverse-distance weights do not separate: the tables hold the
+        // node offsets, and the A operand forms the weight per pair
+        const double u = k < kn ? (xaxis ? ux[k] : uy[k]) : 0.0;
+        for (int c = 0; c < cnt; ++c)
+          g[c * KS + k] = k < kn ? u - (double)(c - mid) * s : __builtin_inf();
+      } else if (k < kn) {
         const double u = xaxis ? ux[k] : uy[k];
         const double t = u / s + (double)mid;
         int cs = (int)fmin(fmax(rint(t), 0.0), (double)(cnt - 1));
@@ -280,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-          const double a = ax[j] * ay[t][j];
+          const double a = INV ? invpow_weight(ax[j], ay[t][j], p.alpha) : ax[j] * ay[t][j];
 #pragma unroll
           for (int q = 0; q < NT; ++q)
             acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[q][j], acc[t][q], 0, 0, 0);
@@ -336,7 +363,7 @@ __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stri
   }
 }
 
-template <int DEG, int NT, int R>
+template <int DEG, int NT, int R, bool INV>
 hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   using L = F64Layout<DEG, NT, R>;
   F64Params p = prm;
@@ -344,35 +371,44 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   const int tiles_y = (p.H + L::kRows - 1) / L::kRows;
   p.tiles_x = tiles_x;
   const size_t lds_bytes = sizeof(double) * (size_t)L::kDoubles;
-  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R>,
+  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, INV>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
-  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R>), dim3((unsigned)blocks), dim3(kThreads),
+  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, INV>), dim3((unsigned)blocks), dim3(kThreads),
                      lds_bytes, s, p);
   return hipGetLastError();
 }
 
 // R (row strips per wave) trades accumulator registers against the number
 // of Gaussian factors per tile.
-template <int DEG, int NT>
+template <int DEG, int NT, bool INV>
 hipError_t launch_nt(const F64Params& p, hipStream_t s) {
   constexpr int R = NT <= 3 ? 4 : (NT <= 6 ? 2 : 1);
-  return launch_impl<DEG, NT, R>(p, s);
+  return launch_impl<DEG, NT, R, INV>(p, s);
 }
 
-template <int DEG>
+template <int DEG, bool INV>
 hipError_t launch_deg(const F64Params& p, int nt, hipStream_t s) {
   switch (nt) {
-    case 1: return launch_nt<DEG, 1>(p, s);
-    case 2: return launch_nt<DEG, 2>(p, s);
-    case 3: return launch_nt<DEG, 3>(p, s);
-    case 4: return launch_nt<DEG, 4>(p, s);
-    case 5: case 6: return launch_nt<DEG, 6>(p, s);
-    case 7: case 8: return launch_nt<DEG, 8>(p, s);
-    case 9: case 10: case 11: case 12: return launch_nt<DEG, 12>(p, s);
-    default: return launch_nt<DEG, 16>(p, s);
+    case 1: return launch_nt<DEG, 1, INV>(p, s);
+    case 2: return launch_nt<DEG, 2, INV>(p, s);
+    case 3: return launch_nt<DEG, 3, INV>(p, s);
+    case 4: return launch_nt<DEG, 4, INV>(p, s);
+    case 5: case 6: return launch_nt<DEG, 6, INV>(p, s);
+    case 7: case 8: return launch_nt<DEG, 8, INV>(p, s);
+    case 9: case 10: case 11: case 12: return launch_nt<DEG, 12, INV>(p, s);
+    default: return launch_nt<DEG, 16, INV>(p, s);
+  }
+}
+
+template <bool INV>
+hipError_t launch_kind(const F64Params& p, int degree, int nt, hipStream_t s) {
+  switch (degree) {
+    case 0: return launch_deg<0, INV>(p, nt, s);
+    case 1: return launch_deg<1, INV>(p, nt, s);
+    default: return launch_deg<2, INV>(p, nt, s);
   }
 }
 
@@ -390,6 +426,7 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   p.F = F;
   p.h = a.h;
   p.inv_h = 1.0 / a.h;
+  p.alpha = a.alpha;
   p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;
   p.W = a.W; p.H = a.H;
   p.tiles_x = 0;
@@ -397,11 +434,8 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   p.floor_w = a.floor_w;
   p.fields = a.fields;
   p.deg_out = a.deg_out;
-  switch (a.degree) {
-    case 0: return launch_deg<0>(p, nt, stream);
-    case 1: return launch_deg<1>(p, nt, stream);
-    default: return launch_deg<2>(p, nt, stream);
-  }
+  if (a.wkind == 2) return launch_kind<true>(p, a.degree, nt, stream);   // inverse distance
+  return launch_kind<false>(p, a.degree, nt, stream);                    // Gaussian
 }
 
 }  // namespace mls

@@ -28,7 +28,8 @@ struct FitArgs {
 __host__ __device__ constexpr int basis_terms(int deg) { return deg == 0 ? 1 : (deg == 1 ? 3 : 6); }
 __host__ __device__ constexpr int moment_terms(int deg) { return deg == 0 ? 1 : (deg == 1 ? 6 : 15); }
 
-// Float64 matrix-core fit (Gaussian weight).  Returns a hipError_t.
+// Float64 matrix-core fit (Gaussian or inverse-distance weight).  Returns a
+// hipError_t.  With the inverse-distance weight, launch_hits must follow.
 hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream);
 
 // Cell-ordered payload for compactly supported weights (from launch_cells).
@@ -114,6 +115,25 @@ struct CellArgs {
   uint32_t* thist;         // [256 * radix_blocks(tiles)]
 };
 int64_t radix_blocks(int64_t n);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits; the
+// result ends in (k0, v0); (k1, v1) and hist[256 * radix_blocks(n)] are scratch.
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
+                            int bits, uint32_t* hist, hipStream_t s);
+
+// Exact hits of the inverse-distance weight: nodes on data points take the
+// mean of those points' values and degree code 254.
+struct HitArgs {
+  const float* pts;        // [n][2]
+  const float* vals;       // [n][D]
+  int64_t n;
+  int32_t D;
+  double x0, y0, dx, dy;   // dx, dy nonzero
+  int32_t W, H;
+  float* fields;           // [D][H][W]
+  uint8_t* deg_out;        // [H][W] or null
+  uint32_t *keys, *keys2, *idx, *idx2, *hist;   // scratch (n, n, n, n, 256 radix_blocks(n))
+};
+hipError_t launch_hits(const HitArgs& a, hipStream_t s);
 hipError_t launch_cells(const CellArgs& a, hipStream_t stream);
 
 // Scratch layout of one mls_fit call (byte offsets into one buffer).

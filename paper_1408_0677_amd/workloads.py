@@ -186,6 +186,18 @@ def c5(seed=0, grid_side=4096, n=1_000_000, d=16):
                     "wendland", 0.01, pixel_grid(grid_side), "bf16", n_iso=16)
 
 
+def t1(n, seed=0):
+    """Shape of the paper's timing table (Table 1): a 600 x 600 canvas, N
+    uniform points, two attributes, the linear basis with the paper's own
+    inverse-distance weight (Eq. 4, alpha = 1)."""
+    rng = np.random.default_rng(seed + n)
+    pts = uniform_points(rng, n)
+    vals = smooth_fields(rng, pts, 2)
+    return Workload(f"t1_n{n}_d2_linear_invpow_a1_600", pts.astype(np.float32),
+                    vals.astype(np.float32), "linear", "invpow", 0.05, pixel_grid(600),
+                    "fp64", n_iso=10, alpha=1.0)
+
+
 def c4_requests(seed=0, count=256):
     """Request mix of the served form: sizes, bases and bandwidths drawn at
     random; the bandwidth puts about 20 (linear) or 40 (quadratic) points
