@@ -123,7 +123,7 @@ def test_errors_are_isolated(torch_dev):
     pid = srv.put_points(P, V)
     grid = {"x0": 0.0, "y0": 0.0, "dx": 0.02, "dy": 0.02, "width": 40, "height": 40}
     out = torch.empty((3, 40, 40), device="cuda")
-    bad = srv.submit(pid, grid, out, weight="invpow")            # unsupported kind
+    bad = srv.submit(pid, grid, out, weight="wendland")          # unsupported with f64
     good = srv.submit(pid, grid, torch.empty((3, 40, 40), device="cuda"), h=0.1)
     rb = srv.wait(bad)
     rg = srv.wait(good)
