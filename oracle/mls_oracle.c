@@ -101,12 +101,19 @@ static double eval_weight(int kind, double rho2, double h, double alpha) {
  * Solve the normal equations of one position through the degree ladder.
  * M is m x m (row-major, full), R is m x D (row-major).  Writes D values
  * to out[d * out_stride], the accepted degree and the smallest accepted
- * equilibrated pivot.
+ * equilibrated pivot.  If grad is not NULL it also receives the gradient of
+ * the local fit at the position, (c_1, c_2) / h for each attribute (the
+ * basis is centred on the position and scaled by h, so these are the
+ * fitted slopes; zero when the ladder accepts the constant basis, NaN where
+ * the value is NaN), at grad[(2 d + axis) * out_stride].
  */
 static void ladder_solve(const double* M, const double* R, int m, int D,
-                         double tau, double floor_w, double* out,
-                         int64_t out_stride, uint8_t* deg_out, double* dmin_out) {
+                         double tau, double floor_w, double h, double* out,
+                         int64_t out_stride, double* grad, uint8_t* deg_out,
+                         double* dmin_out) {
   if (!(M[0] >= floor_w)) {
+    if (grad)
+      for (int d = 0; d < 2 * D; ++d) grad[(int64_t)d * out_stride] = NAN;
     for (int d = 0; d < D; ++d) out[(int64_t)d * out_stride] = NAN;
     *deg_out = OR_DEG_NAN;
     *dmin_out = 0.0;
@@ -153,12 +160,18 @@ static void ladder_solve(const double* M, const double* R, int m, int D,
         y[r] = v / L[r][r];
       }
       out[(int64_t)d * out_stride] = s[0] * y[0];
+      if (grad) {
+        grad[(int64_t)(2 * d) * out_stride] = mk >= 3 ? s[1] * y[1] / h : 0.0;
+        grad[(int64_t)(2 * d + 1) * out_stride] = mk >= 3 ? s[2] * y[2] / h : 0.0;
+      }
     }
     *deg_out = (uint8_t)k;
     *dmin_out = pmin;
     return;
   }
   /* Unreachable: degree 0 always passes once M_00 >= floor > 0. */
+  if (grad)
+    for (int d = 0; d < 2 * D; ++d) grad[(int64_t)d * out_stride] = NAN;
   for (int d = 0; d < D; ++d) out[(int64_t)d * out_stride] = NAN;
   *deg_out = OR_DEG_NAN;
   *dmin_out = 0.0;
@@ -168,8 +181,8 @@ static void ladder_solve(const double* M, const double* R, int m, int D,
 static void fit_one(const float* pts, const float* vals, int64_t n, int D,
                     int degree, int wkind, double h, double alpha, double px,
                     double py, double tau, double floor_w, double* out,
-                    int64_t out_stride, uint8_t* deg_out, double* dmin_out,
-                    double* work /* m*D */) {
+                    int64_t out_stride, double* grad, uint8_t* deg_out,
+                    double* dmin_out, double* work /* m*D */) {
   int m = terms_for_degree(degree);
   double M[OR_MAXM * OR_MAXM];
   double* R = work;
@@ -186,6 +199,9 @@ static void fit_one(const float* pts, const float* vals, int64_t n, int D,
       }
     }
     if (hits > 0) {
+      /* the field jumps to the points' own value: no slope there */
+      if (grad)
+        for (int d = 0; d < 2 * D; ++d) grad[(int64_t)d * out_stride] = NAN;
       for (int d = 0; d < D; ++d) out[(int64_t)d * out_stride] = R[d] / (double)hits;
       *deg_out = OR_DEG_HIT;
       *dmin_out = 1.0;
@@ -207,7 +223,7 @@ static void fit_one(const float* pts, const float* vals, int64_t n, int D,
   }
   for (int r = 0; r < m; ++r)
     for (int c = 0; c < r; ++c) M[r * m + c] = M[c * m + r];
-  ladder_solve(M, R, m, D, tau, floor_w, out, out_stride, deg_out, dmin_out);
+  ladder_solve(M, R, m, D, tau, floor_w, h, out, out_stride, grad, deg_out, dmin_out);
 }
 
 static int check_common(const float* pts, const float* vals, int64_t n, int D,
@@ -221,13 +237,15 @@ static int check_common(const float* pts, const float* vals, int64_t n, int D,
 
 /*
  * MLS values at arbitrary positions pos[P][2].  Outputs: fields[D][P],
- * degree codes deg[P], smallest accepted pivot dmin[P].
+ * degree codes deg[P], smallest accepted pivot dmin[P], and, if grads is
+ * not NULL, the gradients grads[D][2][P] (see ladder_solve).
  * Returns 0, or -1 on invalid arguments.
  */
 int oracle_fit_at(const float* pts, const float* vals, int64_t n, int32_t D,
                   int32_t degree, int32_t wkind, double h, double alpha,
                   const double* pos, int64_t npos, double tau, double floor_w,
-                  int32_t nthreads, double* fields, uint8_t* deg, double* dmin) {
+                  int32_t nthreads, double* fields, uint8_t* deg, double* dmin,
+                  double* grads) {
   if (check_common(pts, vals, n, D, degree, wkind, h) || !pos || npos < 0 ||
       !fields || !deg || !dmin)
     return -1;
@@ -243,7 +261,8 @@ int oracle_fit_at(const float* pts, const float* vals, int64_t n, int32_t D,
 #pragma omp for schedule(static)
     for (int64_t k = 0; k < npos; ++k)
       fit_one(pts, vals, n, D, degree, wkind, h, alpha, pos[2 * k], pos[2 * k + 1],
-              tau, floor_w, fields + k, npos, deg + k, dmin + k, work);
+              tau, floor_w, fields + k, npos, grads ? grads + k : NULL, deg + k,
+              dmin + k, work);
     free(work);
   }
   return 0;
@@ -253,14 +272,15 @@ int oracle_fit_at(const float* pts, const float* vals, int64_t n, int32_t D,
  * MLS values at grid nodes.  Node (r, c) sits at (x0 + c*dx, y0 + r*dy);
  * pixels[] lists linear node indices r*W + c (NULL means all H*W nodes in
  * row-major order, npix = H*W).  Outputs fields[D][npix], deg[npix],
- * dmin[npix].  Returns 0, or -1 on invalid arguments.
+ * dmin[npix], and, if grads is not NULL, grads[D][2][npix].  Returns 0, or
+ * -1 on invalid arguments.
  */
 int oracle_fit_grid(const float* pts, const float* vals, int64_t n, int32_t D,
                     int32_t degree, int32_t wkind, double h, double alpha,
                     double x0, double y0, double dx, double dy, int32_t W,
                     int32_t H, const int64_t* pixels, int64_t npix, double tau,
                     double floor_w, int32_t nthreads, double* fields,
-                    uint8_t* deg, double* dmin) {
+                    uint8_t* deg, double* dmin, double* grads) {
   if (check_common(pts, vals, n, D, degree, wkind, h) || W < 1 || H < 1 ||
       !fields || !deg || !dmin)
     return -1;
@@ -285,7 +305,7 @@ int oracle_fit_grid(const float* pts, const float* vals, int64_t n, int32_t D,
       int64_t r = lin / W, c = lin % W;
       double px = x0 + (double)c * dx, py = y0 + (double)r * dy;
       fit_one(pts, vals, n, D, degree, wkind, h, alpha, px, py, tau, floor_w,
-              fields + k, npix, deg + k, dmin + k, work);
+              fields + k, npix, grads ? grads + k : NULL, deg + k, dmin + k, work);
     }
     free(work);
   }

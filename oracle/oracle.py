@@ -58,11 +58,11 @@ def _load():
     P = ctypes.c_void_p
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     lib.oracle_fit_at.argtypes = [P, P, i64, i32, i32, i32, f64, f64, P, i64,
-                                  f64, f64, i32, P, P, P]
+                                  f64, f64, i32, P, P, P, P]
     lib.oracle_fit_at.restype = ctypes.c_int
     lib.oracle_fit_grid.argtypes = [P, P, i64, i32, i32, i32, f64, f64, f64, f64,
                                     f64, f64, i32, i32, P, i64, f64, f64, i32, P,
-                                    P, P]
+                                    P, P, P]
     lib.oracle_fit_grid.restype = ctypes.c_int
     for name in ("oracle_contour_f64", "oracle_contour_f32"):
         fn = getattr(lib, name)
@@ -86,13 +86,13 @@ def _prep(points, values):
 
 
 def fit_at(points, values, positions, basis="linear", weight="gaussian", h=0.05,
-           alpha=1.0, tau=1e-8, weight_floor=1e-6, threads=0):
+           alpha=1.0, tau=1e-8, weight_floor=1e-6, threads=0, grads=False):
     """MLS values at arbitrary positions.
 
     ``points`` (N, 2) and ``values`` (N, D) are rounded to float32 first (the
     oracle sees exactly the arrays a GPU caller would hand over); positions
     (P, 2) stay float64.  Returns ``(fields (D, P) float64, degree (P,) uint8,
-    dmin (P,) float64)``.
+    dmin (P,) float64)``, plus the gradients (D, 2, P) with ``grads=True``.
     """
     pts, vals = _prep(points, values)
     pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 2)
@@ -101,23 +101,26 @@ def fit_at(points, values, positions, basis="linear", weight="gaussian", h=0.05,
     fields = np.empty((D, P), np.float64)
     deg = np.empty(P, np.uint8)
     dmin = np.empty(P, np.float64)
+    g = np.empty((D, 2, P), np.float64) if grads else None
     rc = _load().oracle_fit_at(_ptr(pts), _ptr(vals), n, D, BASIS_DEGREE[basis],
                                WEIGHT_KINDS[weight], float(h), float(alpha),
                                _ptr(pos), P, float(tau), float(weight_floor),
-                               int(threads), _ptr(fields), _ptr(deg), _ptr(dmin))
+                               int(threads), _ptr(fields), _ptr(deg), _ptr(dmin), _ptr(g))
     if rc != 0:
         raise ValueError("oracle_fit_at rejected its arguments")
-    return fields, deg, dmin
+    return (fields, deg, dmin, g) if grads else (fields, deg, dmin)
 
 
 def fit_grid(points, values, grid, basis="linear", weight="gaussian", h=0.05,
-             alpha=1.0, tau=1e-8, weight_floor=1e-6, pixels=None, threads=0):
+             alpha=1.0, tau=1e-8, weight_floor=1e-6, pixels=None, threads=0, grads=False):
     """MLS values at grid nodes.
 
     ``grid`` is a dict with x0, y0, dx, dy, width, height; node (r, c) sits at
     (x0 + c*dx, y0 + r*dy).  ``pixels`` is an optional array of linear node
     indices r*W + c.  Returns ``(fields, degree, dmin)`` shaped (D, H, W) /
-    (H, W) for the whole grid, or (D, P) / (P,) for a pixel list.
+    (H, W) for the whole grid, or (D, P) / (P,) for a pixel list.  With
+    ``grads=True`` a fourth result holds the gradients of the local fits,
+    (D, 2, H, W) or (D, 2, P).
     """
     pts, vals = _prep(points, values)
     n, D = vals.shape
@@ -130,17 +133,20 @@ def fit_grid(points, values, grid, basis="linear", weight="gaussian", h=0.05,
     fields = np.empty((D, P), np.float64)
     deg = np.empty(P, np.uint8)
     dmin = np.empty(P, np.float64)
+    g = np.empty((D, 2, P), np.float64) if grads else None
     rc = _load().oracle_fit_grid(_ptr(pts), _ptr(vals), n, D, BASIS_DEGREE[basis],
                                  WEIGHT_KINDS[weight], float(h), float(alpha),
                                  float(grid["x0"]), float(grid["y0"]),
                                  float(grid["dx"]), float(grid["dy"]), W, H,
                                  _ptr(pix), P, float(tau), float(weight_floor),
-                                 int(threads), _ptr(fields), _ptr(deg), _ptr(dmin))
+                                 int(threads), _ptr(fields), _ptr(deg), _ptr(dmin),
+                                 _ptr(g))
     if rc != 0:
         raise ValueError("oracle_fit_grid rejected its arguments")
     if pixels is None:
-        return fields.reshape(D, H, W), deg.reshape(H, W), dmin.reshape(H, W)
-    return fields, deg, dmin
+        out = (fields.reshape(D, H, W), deg.reshape(H, W), dmin.reshape(H, W))
+        return out + (g.reshape(D, 2, H, W),) if grads else out
+    return (fields, deg, dmin, g) if grads else (fields, deg, dmin)
 
 
 def contour(fields, grid, iso, f32=False):

@@ -40,9 +40,15 @@ MUTATIONS = [
      "case 2: va = v2; vb = v3; break;"),
     ("segment reversed", "{0, 3}, {1, 0}, {1, 3}", "{3, 0}, {1, 0}, {1, 3}"),
     ("right edge x off by one", "*x = x0 + (double)(j + 1) * dx;", "*x = x0 + (double)j * dx;"),
+    ("gradient equilibration factor", "mk >= 3 ? s[1] * y[1] / h : 0.0",
+     "mk >= 3 ? s[0] * y[1] / h : 0.0"),
+    ("gradient without 1/h", "mk >= 3 ? s[2] * y[2] / h : 0.0", "mk >= 3 ? s[2] * y[2] : 0.0"),
+    ("gradient axes swapped", "mk >= 3 ? s[1] * y[1] / h : 0.0",
+     "mk >= 3 ? s[2] * y[2] / h : 0.0"),
 ]
 
-PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_contour_pins.py"]
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_contour_pins.py",
+             "tests/test_oracle_grad_pins.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
