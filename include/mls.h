@@ -190,6 +190,24 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
                    void* stream);
 
 /*
+ * mls_fit plus the slope of each node's local fit (the gradient that the
+ * adaptive contour-line mapping of Sec. 3.4 follows): for the basis centred
+ * on the node and scaled by h, d f_d / dx = c_1 / h and d f_d / dy = c_2 / h.
+ *  d_grad  float32 [d][2][height][width] output, device, not NULL: plane
+ *          2 d holds d f_d / dx, plane 2 d + 1 holds d f_d / dy.  Zero where
+ *          the ladder accepts the constant basis; NaN where the field is
+ *          NaN and at exact hits of the inverse-distance weight (the field
+ *          jumps to the points' value there).
+ * Other arguments, errors and scratch as mls_fit.  The float64 path runs a
+ * separate kernel variant (one workgroup per CU instead of two).
+ */
+mls_status mls_fit_grad(mls_context* ctx, const float* d_points, const float* d_values,
+                        int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                        const mls_grid* grid, int32_t precision,
+                        const mls_solve_opts* opts, float* d_fields, float* d_grad,
+                        uint8_t* d_degree, void* stream);
+
+/*
  * Device scratch bytes mls_fit needs for this request (0 for MLS_PREC_F64);
  * 0 also for invalid arguments.
  */

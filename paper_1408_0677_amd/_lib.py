@@ -19,7 +19,7 @@ EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_context_reserve", "mls_server_create", "mls_server_destroy",
            "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
            "mls_server_poll", "mls_server_wait", "mls_server_last_error",
-           "mls_server_tuning", "mls_server_tuned_classes")
+           "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad")
 
 
 class MlsGrid(ctypes.Structure):
@@ -77,6 +77,10 @@ def load():
                             ctypes.POINTER(MlsGrid), i32,
                             ctypes.POINTER(MlsSolveOpts), P, P, P]
     lib.mls_fit.restype = ctypes.c_int
+    lib.mls_fit_grad.argtypes = [P, P, P, i64, i32, i32, ctypes.POINTER(MlsWeight),
+                                 ctypes.POINTER(MlsGrid), i32, ctypes.POINTER(MlsSolveOpts),
+                                 P, P, P, P]
+    lib.mls_fit_grad.restype = ctypes.c_int
     lib.mls_contour.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P, i64,
                                 ctypes.POINTER(i64), P]
     lib.mls_contour.restype = ctypes.c_int

@@ -119,6 +119,36 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
     return out, degree_out
 
 
+def fit_grad(points, values, grid: dict, basis: str = "linear", weight: str = "gaussian",
+             h: float = 0.05, alpha: float = 1.0, precision: str = "f64",
+             pivot_tol: float = 1e-8, weight_floor: float = 1e-6, lp_terms: int = 0,
+             lp_slab: int = 0, ctx: Context | None = None, stream=None):
+    """As ``fit``, plus the slopes of the local fits: returns ``(fields (D, H,
+    W), grads (D, 2, H, W), degree (H, W))``; grads[d, 0] = d f_d / dx,
+    grads[d, 1] = d f_d / dy."""
+    import torch
+    assert points.dtype == torch.float32 and values.dtype == torch.float32
+    assert points.is_contiguous() and values.is_contiguous()
+    if values.dim() == 1:
+        values = values.view(-1, 1)
+    n, d = values.shape
+    W, H = int(grid["width"]), int(grid["height"])
+    out = torch.empty((d, H, W), dtype=torch.float32, device=points.device)
+    grads = torch.empty((d, 2, H, W), dtype=torch.float32, device=points.device)
+    degree = torch.empty((H, W), dtype=torch.uint8, device=points.device)
+    ctx = ctx or default_context(points.device.index)
+    g = grid_struct(grid)
+    wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
+    opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor), int(lp_terms),
+                             int(lp_slab))
+    st = _lib.load().mls_fit_grad(ctx.handle, _ptr(points), _ptr(values), n, d, BASIS[basis],
+                                  ctypes.byref(wt), ctypes.byref(g), PRECISION[precision],
+                                  ctypes.byref(opts), _ptr(out), _ptr(grads), _ptr(degree),
+                                  _stream_handle(stream))
+    _check(st, "mls_fit_grad")
+    return out, grads, degree
+
+
 CAPACITY_ERROR = -3
 
 

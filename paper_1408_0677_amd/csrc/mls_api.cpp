@@ -223,11 +223,12 @@ void mls_context_destroy(mls_context* ctx) {
   delete ctx;
 }
 
-mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
-                   int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
-                   const mls_grid* grid, int32_t precision, const mls_solve_opts* opts,
-                   float* d_fields, uint8_t* d_degree, void* stream) {
-  g_last_error[0] = '\0';
+// mls_fit and mls_fit_grad: d_grad (slopes of the local fits) may be NULL.
+static mls_status fit_impl(mls_context* ctx, const float* d_points, const float* d_values,
+                           int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                           const mls_grid* grid, int32_t precision,
+                           const mls_solve_opts* opts, float* d_fields, float* d_grad,
+                           uint8_t* d_degree, void* stream) {
   // ---- arguments, checked without touching the device ----
   if (basis < MLS_BASIS_CONSTANT || basis > MLS_BASIS_QUADRATIC)
     return fail(MLS_ERR_INVALID_ARG, "basis %d is not an mls_basis", basis);
@@ -296,6 +297,7 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   if ((st = check_device_ptr(ctx, d_values, "d_values")) != MLS_OK) return st;
   if ((st = check_device_ptr(ctx, d_fields, "d_fields")) != MLS_OK) return st;
   if (d_degree && (st = check_device_ptr(ctx, d_degree, "d_degree")) != MLS_OK) return st;
+  if (d_grad && (st = check_device_ptr(ctx, d_grad, "d_grad")) != MLS_OK) return st;
 
   mls::FitArgs a;
   a.pts = d_points;
@@ -317,6 +319,7 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
   a.lp_slab = slab;
   a.fields = d_fields;
   a.deg_out = d_degree;
+  a.grads = d_grad;
   hipStream_t s = (hipStream_t)stream;
   if (precision == MLS_PREC_F64) {
     mls::FitPlan plan{};
@@ -342,6 +345,7 @@ mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_value
       hta.H = grid->height;
       hta.fields = d_fields;
       hta.deg_out = d_degree;
+      hta.grads = d_grad;
       hta.keys = (uint32_t*)(base + plan.o_keys);
       hta.keys2 = (uint32_t*)(base + plan.o_keys2);
       hta.idx = (uint32_t*)(base + plan.o_perm);
@@ -437,6 +441,25 @@ mls_status mls_context_reserve(mls_context* ctx, size_t bytes) {
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return device_fail(e, "hipSetDevice");
   return ensure_scratch(ctx->fit_scratch, bytes);
+}
+
+mls_status mls_fit(mls_context* ctx, const float* d_points, const float* d_values,
+                   int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                   const mls_grid* grid, int32_t precision, const mls_solve_opts* opts,
+                   float* d_fields, uint8_t* d_degree, void* stream) {
+  g_last_error[0] = '\0';
+  return fit_impl(ctx, d_points, d_values, n, d, basis, weight, grid, precision, opts, d_fields,
+                  nullptr, d_degree, stream);
+}
+
+mls_status mls_fit_grad(mls_context* ctx, const float* d_points, const float* d_values,
+                        int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                        const mls_grid* grid, int32_t precision, const mls_solve_opts* opts,
+                        float* d_fields, float* d_grad, uint8_t* d_degree, void* stream) {
+  g_last_error[0] = '\0';
+  if (!d_grad) return fail(MLS_ERR_INVALID_ARG, "d_grad is NULL");
+  return fit_impl(ctx, d_points, d_values, n, d, basis, weight, grid, precision, opts, d_fields,
+                  d_grad, d_degree, stream);
 }
 
 size_t mls_fit_scratch_bytes(int64_t n, int32_t d, int32_t precision, const mls_weight* weight,

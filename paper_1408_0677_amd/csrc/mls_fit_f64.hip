@@ -80,6 +80,7 @@ struct F64Params {
   double tau, floor_w;
   float* fields;
   uint8_t* deg_out;
+  float* grads;        // [D][2][H][W] or null
 };
 
 template <int DEG, int NT, int R>
@@ -106,7 +107,7 @@ struct F64Layout {
   static constexpr int kDoubles = kChunk > kEpi ? kChunk : kEpi;
 };
 
-template <int DEG, int R>
+template <int DEG, int R, bool GRAD>
 __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
                                  int wave, int r0, int c0, int rows, int64_t plane);
 
@@ -130,7 +131,10 @@ __device__ __forceinline__ double invpow_weight(double ox, double oy, double alp
   return ldexp((double)exp2f((float)(e - ip)), (int)ip);
 }
 
-template <int DEG, int NT, int R, bool INV>
+// GRAD kernels also write the slopes of the local fits (the extra solves
+// raise the epilogue's register count, so they are separate instantiations
+// and the plain kernels keep two workgroups per CU).
+template <int DEG, int NT, int R, bool INV, bool GRAD>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
   using L = F64Layout<DEG, NT, R>;
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
@@ -339,13 +343,14 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
           }
     }
     __syncthreads();
-    if (mine) solve_tile_nodes<DEG, R>(p, epi, L::kEpiStride, lane, wave, r0, c0, L::kRows, plane);
+    if (mine)
+      solve_tile_nodes<DEG, R, GRAD>(p, epi, L::kEpiStride, lane, wave, r0, c0, L::kRows, plane);
     __syncthreads();
   }
 }
 
 // One node per lane: the float64 ladder solve of the nodes of one wave.
-template <int DEG, int R>
+template <int DEG, int R, bool GRAD>
 __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
                                  int wave, int r0, int c0, int rows, int64_t plane) {
   const int D = p.D;
@@ -358,12 +363,13 @@ __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stri
     const double ey = (double)(wave * R + t - rows / 2) * p.dy * p.inv_h;
     const int64_t off = (int64_t)r * p.W + c;
     uint8_t code = solve_node<DEG>(epi + node * stride, D, ex, ey, p.tau, p.floor_w,
-                                   p.fields + off, plane);
+                                   p.fields + off, plane, nullptr, nullptr, 1.0,
+                                   GRAD ? p.grads + off : nullptr, p.inv_h);
     if (p.deg_out) p.deg_out[off] = code;
   }
 }
 
-template <int DEG, int NT, int R, bool INV>
+template <int DEG, int NT, int R, bool INV, bool GRAD>
 hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   using L = F64Layout<DEG, NT, R>;
   F64Params p = prm;
@@ -371,12 +377,12 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   const int tiles_y = (p.H + L::kRows - 1) / L::kRows;
   p.tiles_x = tiles_x;
   const size_t lds_bytes = sizeof(double) * (size_t)L::kDoubles;
-  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, INV>,
+  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, INV, GRAD>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
-  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, INV>), dim3((unsigned)blocks), dim3(kThreads),
+  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, INV, GRAD>), dim3((unsigned)blocks), dim3(kThreads),
                      lds_bytes, s, p);
   return hipGetLastError();
 }
@@ -386,7 +392,8 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
 template <int DEG, int NT, bool INV>
 hipError_t launch_nt(const F64Params& p, hipStream_t s) {
   constexpr int R = NT <= 3 ? 4 : (NT <= 6 ? 2 : 1);
-  return launch_impl<DEG, NT, R, INV>(p, s);
+  return p.grads ? launch_impl<DEG, NT, R, INV, true>(p, s)
+                 : launch_impl<DEG, NT, R, INV, false>(p, s);
 }
 
 template <int DEG, bool INV>
@@ -434,6 +441,7 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   p.floor_w = a.floor_w;
   p.fields = a.fields;
   p.deg_out = a.deg_out;
+  p.grads = a.grads;
   if (a.wkind == 2) return launch_kind<true>(p, a.degree, nt, stream);   // inverse distance
   return launch_kind<false>(p, a.degree, nt, stream);                    // Gaussian
 }

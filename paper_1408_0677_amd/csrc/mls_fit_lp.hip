@@ -111,6 +111,7 @@ struct LPParams {
   float cutoff2;          // points with u^2 beyond this get no features
   float* fields;
   uint8_t* deg_out;
+  float* grads;           // [D][2][H][W] or null
   const uint32_t* cell_start;
   const uint32_t* torder;
   int ncx, ncy;
@@ -511,7 +512,10 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
       uint8_t code = solve_node<DEG, float>(e + node * L::kEpiStride, Ds, ex, ey, p.tau,
                                             p.floor_w, p.fields + (int64_t)d0 * plane + off,
                                             plane, p.shift + d0, p.scale + d0,
-                                            (double)WeightGain<T>::value);
+                                            (double)WeightGain<T>::value,
+                                            p.grads ? p.grads + (int64_t)(2 * d0) * plane + off
+                                                    : nullptr,
+                                            p.inv_hd);
       if (p.deg_out && slab == 0) p.deg_out[off] = code;
     }
   }
@@ -655,6 +659,7 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
   p.cutoff2 = (float)(reach * reach);
   p.fields = a.fields;
   p.deg_out = a.deg_out;
+  p.grads = a.grads;
   p.cell_start = nullptr;
   p.torder = nullptr;
   p.ncx = p.ncy = 0;

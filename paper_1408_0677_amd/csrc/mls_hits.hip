@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void hit_keys_kernel(const float* pts, int64_t
 __global__ __launch_bounds__(256) void hit_mean_kernel(const uint32_t* keys, const uint32_t* idx,
                                                        int64_t n, uint32_t none,
                                                        const float* vals, int D, int64_t plane,
-                                                       float* fields, uint8_t* deg) {
+                                                       float* fields, uint8_t* deg,
+                                                       float* grads) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const uint32_t k = keys[i];
@@ -58,6 +59,9 @@ __global__ __launch_bounds__(256) void hit_mean_kernel(const uint32_t* keys, con
     fields[(int64_t)d * plane + k] = (float)(s / cnt);
   }
   if (deg) deg[k] = 254;
+  // the field jumps to the points' own value there: no slope
+  if (grads)
+    for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane + k] = __builtin_nanf("");
 }
 
 }  // namespace
@@ -72,7 +76,7 @@ hipError_t launch_hits(const HitArgs& a, hipStream_t s) {
   hipError_t e = radix_sort_pairs(a.keys, a.idx, a.keys2, a.idx2, a.n, bits, a.hist, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(hit_mean_kernel, dim3(gb), dim3(256), 0, s, a.keys, a.idx, a.n, none, a.vals,
-                     a.D, (int64_t)a.W * a.H, a.fields, a.deg_out);
+                     a.D, (int64_t)a.W * a.H, a.fields, a.deg_out, a.grads);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct FitArgs {
   float* fields;        // [D][H][W]
   uint8_t* deg_out;     // [H][W] or null
   int32_t lp_slab;      // 16-bit paths: attributes per slab, 0 = lp_slab_plan's choice
+  float* grads;         // [D][2][H][W] slopes of the local fits, or null
 };
 
 // Number of basis terms m and of distinct moment monomials for a degree.
@@ -131,6 +132,7 @@ struct HitArgs {
   int32_t W, H;
   float* fields;           // [D][H][W]
   uint8_t* deg_out;        // [H][W] or null
+  float* grads;            // [D][2][H][W] or null (NaN at hit nodes)
   uint32_t *keys, *keys2, *idx, *idx2, *hist;   // scratch (n, n, n, n, 256 radix_blocks(n))
 };
 hipError_t launch_hits(const HitArgs& a, hipStream_t s);

@@ -13,6 +13,9 @@
 // the definition states, and the value at the node is
 //   field_d = e_0^T M_p'^{-1} R_p' = y^T R_t,  y = T'^T z,  z = M_p'^{-1} e_0
 // so one factorisation and D dot products of length m give all D fields.
+// The slope of the local fit at the node is (c_1, c_2) / h with
+// c_j = e_j^T M_p'^{-1} R_p' = y_j^T R_t, y_j = T'^T M_p'^{-1} e_j: two more
+// triangular solves with the same factor (only when gradients are asked for).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,17 +55,22 @@ __device__ __forceinline__ double shift_entry(int r, int c, double ex, double ey
 // code.  If `shift` is given, the attributes were fitted as
 // (f_d - shift[d]) / scale[d] and the value is mapped back.  `wscale`
 // divides the weight sum before the floor test (weights that were scaled
-// by a common factor).
+// by a common factor).  If `grads` is given, the slopes d f_d / dx and
+// d f_d / dy go to grads[(2 d) * plane] and grads[(2 d + 1) * plane]
+// (zero when the constant basis is accepted, NaN where the field is).
 template <int DEG, typename Acc>
 __device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, double ey,
                               double tau, double floor_w, float* fields,
                               int64_t plane, const float* shift = nullptr,
-                              const float* scale = nullptr, double wscale = 1.0) {
+                              const float* scale = nullptr, double wscale = 1.0,
+                              float* grads = nullptr, double inv_h = 1.0) {
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
   constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
   const double sumw = (double)g[0] / wscale;
   if (!(sumw >= floor_w)) {
     for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
+    if (grads)
+      for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane] = __builtin_nan("");
     return 255;
   }
   double Mt[m][m];
@@ -163,11 +171,57 @@ __device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, do
         if (r < mk) v += T[r][c] * (s[r] * w[r]);
       y[c] = v;
     }
+    if (grads) {
+      // slopes: the same two triangular solves with S e_1 and S e_2
+      const Acc* Rg = g + nmom;
+#pragma unroll 1
+      for (int a = 1; a <= 2; ++a) {
+        double ya[m];
+#pragma unroll
+        for (int c = 0; c < m; ++c) ya[c] = 0.0;
+        if (mk >= 3) {
+#pragma unroll
+          for (int r = 0; r < m; ++r) {
+            if (r >= mk) continue;
+            double v = r == a ? s[r] : 0.0;
+#pragma unroll
+            for (int c = 0; c < r; ++c) v -= L[r][c] * q[c];
+            q[r] = v / L[r][r];
+          }
+#pragma unroll
+          for (int r = m - 1; r >= 0; --r) {
+            if (r >= mk) continue;
+            double v = q[r];
+#pragma unroll
+            for (int c = r + 1; c < m; ++c)
+              if (c < mk) v -= L[c][r] * w[c];
+            w[r] = v / L[r][r];
+          }
+#pragma unroll
+          for (int c = 0; c < m; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int r = 0; r < m; ++r)
+              if (r < mk) v += T[r][c] * (s[r] * w[r]);
+            ya[c] = v;
+          }
+        }
+        for (int d = 0; d < D; ++d) {
+          double v = 0.0;
+#pragma unroll
+          for (int c = 0; c < m; ++c) v += ya[c] * (double)Rg[c * D + d];
+          if (scale) v *= (double)scale[d];
+          grads[(int64_t)(2 * d + a - 1) * plane] = (float)(v * inv_h);
+        }
+      }
+    }
     accepted = kd;
     break;
   }
   if (accepted < 0) {  // only when sum w == 0 passes a zero floor
     for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
+    if (grads)
+      for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane] = __builtin_nan("");
     return 255;
   }
   const Acc* R = g + nmom;

@@ -1,0 +1,123 @@
+"""GPU parity of the slopes of the local fits (mls_fit_grad) against the
+FP64 oracle's gradient output.  Error measure: |g_gpu - g_oracle| * h / S_d
+(S_d the attribute's input range), over nodes where both sides accept the
+same degree >= 1 and the oracle's d_min passes.  Bounds: 1e-5 for the
+float64 path, GRAD_LP for the 16-bit paths (smooth attributes)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GRAD_LP = 5e-3
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def gpu_fit_grad(torch, pts, vals, grid, **kw):
+    from paper_1408_0677_amd import api
+    P = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+    V = torch.from_numpy(np.ascontiguousarray(vals, np.float32)).cuda()
+    f, g, d = api.fit_grad(P, V, grid, **kw)
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), g.cpu().numpy(), d.cpu().numpy()
+
+
+def grad_error(g, deg, og, od, dm, vals, h, dmin_pass):
+    vals = np.asarray(vals, np.float64)
+    S = vals.max(0) - vals.min(0)
+    S = np.where(S > 0, S, 1.0)
+    D = vals.shape[1]
+    g = g.reshape(D, 2, -1)
+    og = og.reshape(D, 2, -1)
+    ok = (deg.ravel() == od.ravel()) & (od.ravel() >= 1) & (od.ravel() < 254) & \
+        (dm.ravel() >= dmin_pass)
+    err = np.abs(g[:, :, ok] - og[:, :, ok]) * h / S[:, None, None]
+    return (float(err.max()) if ok.any() else 0.0), int(ok.sum())
+
+
+@pytest.mark.parametrize("basis", ["constant", "linear", "quadratic"])
+def test_grad_f64_matches_oracle(torch_dev, oracle, basis):
+    from paper_1408_0677_amd import workloads as wl
+    note(f"case grad f64 {basis}")
+    w = wl.c1()
+    F, G, deg = gpu_fit_grad(torch_dev, w.points, w.values, w.grid, basis=basis, h=w.h)
+    of, od, dm, og = oracle.fit_grid(w.points, w.values, w.grid, basis=basis, h=w.h,
+                                     grads=True)
+    err, count = grad_error(G, deg, og, od, dm, w.values, w.h, 1e-3)
+    note(f"max scaled gradient error {err:.3e} over {count} nodes")
+    assert np.array_equal(deg, od)
+    if basis == "constant":
+        det = deg != 255
+        assert np.all(G[:, :, det] == 0.0)
+    else:
+        assert count > 10000
+        assert err <= 1e-5
+    und = deg == 255
+    assert np.all(np.isnan(G[:, :, und]))
+
+
+def test_grad_kernel_keeps_fields_bitwise(torch_dev):
+    """The gradient variant of the float64 kernel computes the fields with the
+    same arithmetic as the plain one."""
+    from paper_1408_0677_amd import api, workloads as wl
+    note("case grad fields bitwise")
+    w = wl.c2(grid_side=256)
+    F, G, deg = gpu_fit_grad(torch_dev, w.points, w.values, w.grid, basis=w.basis, h=w.h)
+    P = torch_dev.from_numpy(w.points).cuda()
+    V = torch_dev.from_numpy(w.values).cuda()
+    f2, d2 = api.fit(P, V, w.grid, basis=w.basis, h=w.h)
+    torch_dev.cuda.synchronize()
+    assert np.array_equal(d2.cpu().numpy(), deg)
+    assert np.array_equal(f2.cpu().numpy().view(np.uint32), F.view(np.uint32))
+
+
+def test_grad_invpow_hits(torch_dev, oracle):
+    """Inverse-distance weight: slopes match the oracle, exact hits give NaN."""
+    from paper_1408_0677_amd import workloads as wl
+    note("case grad invpow hits")
+    rng = np.random.default_rng(4)
+    grid = wl.pixel_grid(64, 32)
+    node = (grid["x0"] + 9 * grid["dx"], grid["y0"] + 7 * grid["dy"])
+    pts = np.concatenate([np.array([node]), rng.random((300, 2))])
+    vals = wl.smooth_fields(rng, pts, 3)
+    F, G, deg = gpu_fit_grad(torch_dev, pts, vals, grid, basis="linear", weight="invpow",
+                             h=0.05)
+    of, od, dm, og = oracle.fit_grid(pts, vals, grid, basis="linear", weight="invpow", h=0.05,
+                                     grads=True)
+    assert deg[7, 9] == 254 and np.all(np.isnan(G[:, :, 7, 9]))
+    err, count = grad_error(G, deg, og, od, dm, vals, 0.05, 1e-3)
+    note(f"max scaled gradient error {err:.3e} over {count} nodes")
+    assert count > 1500 and err <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("basis,weight,h", [("linear", "gaussian", 0.06),
+                                            ("quadratic", "gaussian", 0.08),
+                                            ("quadratic", "wendland", 0.1)])
+def test_grad_lp_matches_oracle(torch_dev, oracle, prec, basis, weight, h):
+    from paper_1408_0677_amd import workloads as wl
+    note(f"case grad {prec} {basis} {weight}")
+    rng = np.random.default_rng(8)
+    pts = rng.random((3000, 2))
+    vals = wl.smooth_fields(rng, pts, 5) * 2.0 + 1.0
+    grid = wl.pixel_grid(128, 96)
+    F, G, deg = gpu_fit_grad(torch_dev, pts, vals, grid, basis=basis, weight=weight, h=h,
+                             precision=prec)
+    of, od, dm, og = oracle.fit_grid(pts, vals, grid, basis=basis, weight=weight, h=h,
+                                     grads=True)
+    err, count = grad_error(G, deg, og, od, dm, vals.astype(np.float32), h, 1e-2)
+    note(f"max scaled gradient error {err:.3e} over {count} nodes")
+    assert count > 5000
+    assert err <= GRAD_LP
