@@ -37,6 +37,10 @@
  *   - Inverse-distance weight with a point exactly at p: the value is the
  *     mean of the coincident points' values (point identity, Sec. 3.3
  *     criterion 2), code 254.
+ *   - Gradient output: the slope of the local fit, (c_1, c_2) / h.
+ *
+ * Rigid MLS (Eq. 9-10) maps a position to 2-vector values q_i by the
+ * rotation-and-translation fit; see rigid_one for the formula and readings.
  *
  * Marching squares (Sec. 3.4 draws contour lines of the MLS output; the
  * extraction rule is this library's reading, the usual 16-case table):
@@ -308,6 +312,131 @@ int oracle_fit_grid(const float* pts, const float* vals, int64_t n, int32_t D,
               fields + k, npix, grads ? grads + k : NULL, deg + k, dmin + k, work);
     }
     free(work);
+  }
+  return bad ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Rigid MLS (Sec. 3.3, Eq. 9-10)                                          */
+/* ---------------------------------------------------------------------- */
+
+/* v^perp for a row vector v = (x, y). */
+static void perp(const double v[2], double out[2]) {
+  out[0] = -v[1];
+  out[1] = v[0];
+}
+
+/*
+ * Rigid MLS of 2-vector values q_i (vals[i][0..1]) at position v = (px, py),
+ * in the paper's notation: p* and q* the weighted centroids (Eq. 7, 8),
+ * dp_i = p_i - p*, dq_i = q_i - q*, dv = v - p*,
+ *   f'(v) = sum_i w_i dq_i [dp_i ; -dp_i^perp] [dv ; -dv^perp]^T
+ *   f(v)  = |dv| f'(v) / |f'(v)| + q*.
+ * Readings: the index on dv in the printed Eq. 10 is a typo (dv does not
+ * depend on i); v^perp = (-y, x); where |f'| = 0 (no rotation defined) or
+ * dv = 0 the value is q*; sum w < floor gives NaN (code 255); an exact hit
+ * of the inverse-distance weight gives the mean of the coincident q_i (code
+ * 254); otherwise code 1.
+ */
+static void rigid_one(const float* pts, const float* vals, int64_t n, int wkind,
+                      double h, double alpha, double px, double py, double floor_w,
+                      double* out, int64_t out_stride, uint8_t* deg_out) {
+  if (wkind == OR_W_INVPOW) {
+    double s0 = 0.0, s1 = 0.0;
+    int64_t hits = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      double dx = (double)pts[2 * i] - px, dy = (double)pts[2 * i + 1] - py;
+      if (dx * dx + dy * dy == 0.0) {
+        s0 += (double)vals[2 * i];
+        s1 += (double)vals[2 * i + 1];
+        ++hits;
+      }
+    }
+    if (hits > 0) {
+      out[0] = s0 / (double)hits;
+      out[out_stride] = s1 / (double)hits;
+      *deg_out = OR_DEG_HIT;
+      return;
+    }
+  }
+  double sw = 0.0, sp[2] = {0.0, 0.0}, sq[2] = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) {
+    double dx = (double)pts[2 * i] - px, dy = (double)pts[2 * i + 1] - py;
+    double w = eval_weight(wkind, dx * dx + dy * dy, h, alpha);
+    sw += w;
+    sp[0] += w * (double)pts[2 * i];
+    sp[1] += w * (double)pts[2 * i + 1];
+    sq[0] += w * (double)vals[2 * i];
+    sq[1] += w * (double)vals[2 * i + 1];
+  }
+  if (!(sw >= floor_w)) {
+    out[0] = NAN;
+    out[out_stride] = NAN;
+    *deg_out = OR_DEG_NAN;
+    return;
+  }
+  const double ps[2] = {sp[0] / sw, sp[1] / sw}, qs[2] = {sq[0] / sw, sq[1] / sw};
+  const double dv[2] = {px - ps[0], py - ps[1]};
+  double dvp[2];
+  perp(dv, dvp);
+  /* B = [dv ; -dv^perp]^T (2 x 2, columns dv and -dv^perp) */
+  const double B[2][2] = {{dv[0], -dvp[0]}, {dv[1], -dvp[1]}};
+  double fr[2] = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) {
+    double dx = (double)pts[2 * i] - px, dy = (double)pts[2 * i + 1] - py;
+    double w = eval_weight(wkind, dx * dx + dy * dy, h, alpha);
+    if (w == 0.0) continue;
+    const double dp[2] = {(double)pts[2 * i] - ps[0], (double)pts[2 * i + 1] - ps[1]};
+    const double dq[2] = {(double)vals[2 * i] - qs[0], (double)vals[2 * i + 1] - qs[1]};
+    double dpp[2];
+    perp(dp, dpp);
+    /* P = [dp ; -dp^perp] (rows dp and -dp^perp) */
+    const double P[2][2] = {{dp[0], dp[1]}, {-dpp[0], -dpp[1]}};
+    double A[2][2];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) A[r][c] = P[r][0] * B[0][c] + P[r][1] * B[1][c];
+    fr[0] += w * (dq[0] * A[0][0] + dq[1] * A[1][0]);
+    fr[1] += w * (dq[0] * A[0][1] + dq[1] * A[1][1]);
+  }
+  const double nf = sqrt(fr[0] * fr[0] + fr[1] * fr[1]);
+  const double nv = sqrt(dv[0] * dv[0] + dv[1] * dv[1]);
+  if (nf > 0.0 && nv > 0.0) {
+    out[0] = nv * fr[0] / nf + qs[0];
+    out[out_stride] = nv * fr[1] / nf + qs[1];
+  } else {
+    out[0] = qs[0];
+    out[out_stride] = qs[1];
+  }
+  *deg_out = 1;
+}
+
+/*
+ * Rigid MLS at grid nodes (as oracle_fit_grid, D = 2 fixed): outputs
+ * fields[2][npix] and deg[npix].  Returns 0, or -1 on invalid arguments.
+ */
+int oracle_rigid_grid(const float* pts, const float* vals, int64_t n, int32_t wkind,
+                      double h, double alpha, double x0, double y0, double dx, double dy,
+                      int32_t W, int32_t H, const int64_t* pixels, int64_t npix,
+                      double floor_w, int32_t nthreads, double* fields, uint8_t* deg) {
+  if (check_common(pts, vals, n, 2, 1, wkind, h) || W < 1 || H < 1 || !fields || !deg)
+    return -1;
+  if (!pixels && npix != (int64_t)W * H) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  int bad = 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < npix; ++k) {
+    int64_t lin = pixels ? pixels[k] : k;
+    if (lin < 0 || lin >= (int64_t)W * H) {
+      bad = 1;
+      continue;
+    }
+    int64_t r = lin / W, c = lin % W;
+    double px = x0 + (double)c * dx, py = y0 + (double)r * dy;
+    rigid_one(pts, vals, n, wkind, h, alpha, px, py, floor_w, fields + k, npix, deg + k);
   }
   return bad ? -1 : 0;
 }

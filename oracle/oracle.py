@@ -64,6 +64,9 @@ def _load():
                                     f64, f64, i32, i32, P, i64, f64, f64, i32, P,
                                     P, P, P]
     lib.oracle_fit_grid.restype = ctypes.c_int
+    lib.oracle_rigid_grid.argtypes = [P, P, i64, i32, f64, f64, f64, f64, f64, f64, i32, i32,
+                                      P, i64, f64, i32, P, P]
+    lib.oracle_rigid_grid.restype = ctypes.c_int
     for name in ("oracle_contour_f64", "oracle_contour_f32"):
         fn = getattr(lib, name)
         fn.argtypes = [P, i32, i32, f64, f64, f64, f64, P, i32, i32, P, P, P, i64]
@@ -147,6 +150,33 @@ def fit_grid(points, values, grid, basis="linear", weight="gaussian", h=0.05,
         out = (fields.reshape(D, H, W), deg.reshape(H, W), dmin.reshape(H, W))
         return out + (g.reshape(D, 2, H, W),) if grads else out
     return (fields, deg, dmin, g) if grads else (fields, deg, dmin)
+
+
+def rigid_grid(points, values, grid, weight="invpow", h=0.05, alpha=1.0,
+               weight_floor=1e-6, pixels=None, threads=0):
+    """Rigid MLS (Eq. 9-10) of 2-vector values (N, 2) at grid nodes.
+    Returns ``(fields (2, H, W), degree (H, W))`` (or (2, P) / (P,) for a
+    pixel list); degree is 1, 254 at exact hits, 255 where undetermined."""
+    pts, vals = _prep(points, values)
+    n, D = vals.shape
+    assert D == 2
+    W, H = int(grid["width"]), int(grid["height"])
+    if pixels is None:
+        pix, P = None, W * H
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        P = pix.shape[0]
+    fields = np.empty((2, P), np.float64)
+    deg = np.empty(P, np.uint8)
+    rc = _load().oracle_rigid_grid(_ptr(pts), _ptr(vals), n, WEIGHT_KINDS[weight], float(h),
+                                   float(alpha), float(grid["x0"]), float(grid["y0"]),
+                                   float(grid["dx"]), float(grid["dy"]), W, H, _ptr(pix), P,
+                                   float(weight_floor), int(threads), _ptr(fields), _ptr(deg))
+    if rc != 0:
+        raise ValueError("oracle_rigid_grid rejected its arguments")
+    if pixels is None:
+        return fields.reshape(2, H, W), deg.reshape(H, W)
+    return fields, deg
 
 
 def contour(fields, grid, iso, f32=False):

@@ -45,10 +45,16 @@ MUTATIONS = [
     ("gradient without 1/h", "mk >= 3 ? s[2] * y[2] / h : 0.0", "mk >= 3 ? s[2] * y[2] : 0.0"),
     ("gradient axes swapped", "mk >= 3 ? s[1] * y[1] / h : 0.0",
      "mk >= 3 ? s[2] * y[2] / h : 0.0"),
+    ("rigid perpendicular turned the other way", "out[0] = -v[1];\n  out[1] = v[0];",
+     "out[0] = v[1];\n  out[1] = -v[0];"),
+    ("rigid length not restored", "out[0] = nv * fr[0] / nf + qs[0];",
+     "out[0] = fr[0] / nf + qs[0];"),
+    ("rigid centroid dropped", "out[out_stride] = nv * fr[1] / nf + qs[1];",
+     "out[out_stride] = nv * fr[1] / nf;"),
 ]
 
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_contour_pins.py",
-             "tests/test_oracle_grad_pins.py"]
+             "tests/test_oracle_grad_pins.py", "tests/test_oracle_rigid_pins.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
