@@ -435,7 +435,7 @@ int oracle_rigid_grid(const float* pts, const float* vals, int64_t n, int32_t wk
       continue;
     }
     int64_t r = lin / W, c = lin % W;
-    double px = x0 + (double)c * dx, py = y0 + (double)r * dy;
+    const double px = x0 + dx * (double)c, py = y0 + dy * (double)r;
     rigid_one(pts, vals, n, wkind, h, alpha, px, py, floor_w, fields + k, npix, deg + k);
   }
   return bad ? -1 : 0;
