@@ -59,7 +59,12 @@ typedef enum {
 typedef enum {
   MLS_BASIS_CONSTANT = 0,  /* m = 1: weighted mean (Eq. 5) */
   MLS_BASIS_LINEAR = 1,    /* m = 3: affine MLS (Eq. 6-8) */
-  MLS_BASIS_QUADRATIC = 2  /* m = 6 */
+  MLS_BASIS_QUADRATIC = 2, /* m = 6 */
+  MLS_BASIS_RIGID = 3       /* rigid MLS of 2-vector values (Eq. 9-10): d = 2,
+                               fields[0..1] are the mapped coordinates; the
+                               rotation-and-translation fit comes from the
+                               linear-basis moments; MLS_PREC_F64 only, no
+                               gradients */
 } mls_basis;
 
 typedef enum {

@@ -10,7 +10,7 @@ import ctypes
 
 from . import _lib
 
-BASIS = {"constant": 0, "linear": 1, "quadratic": 2}
+BASIS = {"constant": 0, "linear": 1, "quadratic": 2, "rigid": 3}
 WEIGHT = {"gaussian": 0, "wendland": 1, "invpow": 2}
 PRECISION = {"f64": 0, "bf16": 1, "fp16": 2}
 STATUS_OK = 0

@@ -50,6 +50,7 @@ int max_d_for(int32_t basis) {
   switch (basis) {
     case MLS_BASIS_CONSTANT: return MLS_MAX_D_CONSTANT;
     case MLS_BASIS_LINEAR: return MLS_MAX_D_LINEAR;
+    case MLS_BASIS_RIGID: return 2;
     default: return MLS_MAX_D_QUADRATIC;
   }
 }
@@ -230,8 +231,10 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
                            const mls_solve_opts* opts, float* d_fields, float* d_grad,
                            uint8_t* d_degree, void* stream) {
   // ---- arguments, checked without touching the device ----
-  if (basis < MLS_BASIS_CONSTANT || basis > MLS_BASIS_QUADRATIC)
+  if (basis < MLS_BASIS_CONSTANT || basis > MLS_BASIS_RIGID)
     return fail(MLS_ERR_INVALID_ARG, "basis %d is not an mls_basis", basis);
+  if (basis == MLS_BASIS_RIGID && d != 2)
+    return fail(MLS_ERR_INVALID_ARG, "d = %d; the rigid map takes 2-vector values", d);
   if (n < 1) return fail(MLS_ERR_INVALID_ARG, "n = %lld; need at least one point", (long long)n);
   if (n > MLS_MAX_N) return fail(MLS_ERR_INVALID_ARG, "n = %lld is too large", (long long)n);
   if (precision < MLS_PREC_F64 || precision > MLS_PREC_FP16)
@@ -285,6 +288,10 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       (weight->kind == MLS_W_WENDLAND_C2 && precision == MLS_PREC_F64))
     return fail(MLS_ERR_UNSUPPORTED, "weight kind %d is not available with precision %d",
                 weight->kind, precision);
+  if (basis == MLS_BASIS_RIGID &&
+      (precision != MLS_PREC_F64 || weight->kind == MLS_W_WENDLAND_C2 || d_grad))
+    return fail(MLS_ERR_UNSUPPORTED, "the rigid map runs on MLS_PREC_F64 with the Gaussian or "
+                "inverse-distance weight, without gradients");
   if (weight->kind == MLS_W_INVPOW && (grid->dx == 0.0 || grid->dy == 0.0))
     return fail(MLS_ERR_UNSUPPORTED, "the inverse-distance weight needs nonzero grid spacing "
                 "(nodes on one position would share their exact hits)");
@@ -304,7 +311,8 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   a.vals = d_values;
   a.n = n;
   a.D = d;
-  a.degree = basis;
+  a.degree = basis == MLS_BASIS_RIGID ? MLS_BASIS_LINEAR : basis;
+  a.rigid = basis == MLS_BASIS_RIGID;
   a.wkind = weight->kind;
   a.h = weight->h;
   a.alpha = weight->alpha;

@@ -81,6 +81,7 @@ struct F64Params {
   float* fields;
   uint8_t* deg_out;
   float* grads;        // [D][2][H][W] or null
+  bool rigid;          // rigid map (EPI 2 kernels)
 };
 
 template <int DEG, int NT, int R>
@@ -107,7 +108,7 @@ struct F64Layout {
   static constexpr int kDoubles = kChunk > kEpi ? kChunk : kEpi;
 };
 
-template <int DEG, int R, bool GRAD>
+template <int DEG, int R, int EPI>
 __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
                                  int wave, int r0, int c0, int rows, int64_t plane);
 
@@ -131,10 +132,11 @@ __device__ __forceinline__ double invpow_weight(double ox, double oy, double alp
   return ldexp((double)exp2f((float)(e - ip)), (int)ip);
 }
 
-// GRAD kernels also write the slopes of the local fits (the extra solves
-// raise the epilogue's register count, so they are separate instantiations
-// and the plain kernels keep two workgroups per CU).
-template <int DEG, int NT, int R, bool INV, bool GRAD>
+// Epilogue EPI: 0 fields, 1 fields and the slopes of the local fits (the
+// extra solves raise the epilogue's register count, so they are separate
+// instantiations and the plain kernels keep two workgroups per CU), 2 the
+// rigid map of 2-vector values from the linear moments.
+template <int DEG, int NT, int R, bool INV, int EPI>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
   using L = F64Layout<DEG, NT, R>;
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
@@ -344,13 +346,13 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     }
     __syncthreads();
     if (mine)
-      solve_tile_nodes<DEG, R, GRAD>(p, epi, L::kEpiStride, lane, wave, r0, c0, L::kRows, plane);
+      solve_tile_nodes<DEG, R, EPI>(p, epi, L::kEpiStride, lane, wave, r0, c0, L::kRows, plane);
     __syncthreads();
   }
 }
 
 // One node per lane: the float64 ladder solve of the nodes of one wave.
-template <int DEG, int R, bool GRAD>
+template <int DEG, int R, int EPI>
 __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stride, int lane,
                                  int wave, int r0, int c0, int rows, int64_t plane) {
   const int D = p.D;
@@ -362,14 +364,18 @@ __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stri
     const double ex = (double)(col - kCols / 2) * p.dx * p.inv_h;
     const double ey = (double)(wave * R + t - rows / 2) * p.dy * p.inv_h;
     const int64_t off = (int64_t)r * p.W + c;
-    uint8_t code = solve_node<DEG>(epi + node * stride, D, ex, ey, p.tau, p.floor_w,
-                                   p.fields + off, plane, nullptr, nullptr, 1.0,
-                                   GRAD ? p.grads + off : nullptr, p.inv_h);
+    uint8_t code;
+    if constexpr (EPI == 2)
+      code = rigid_node(epi + node * stride, ex, ey, p.h, p.floor_w, p.fields + off, plane);
+    else
+      code = solve_node<DEG>(epi + node * stride, D, ex, ey, p.tau, p.floor_w, p.fields + off,
+                             plane, nullptr, nullptr, 1.0, EPI == 1 ? p.grads + off : nullptr,
+                             p.inv_h);
     if (p.deg_out) p.deg_out[off] = code;
   }
 }
 
-template <int DEG, int NT, int R, bool INV, bool GRAD>
+template <int DEG, int NT, int R, bool INV, int EPI>
 hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   using L = F64Layout<DEG, NT, R>;
   F64Params p = prm;
@@ -377,12 +383,12 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   const int tiles_y = (p.H + L::kRows - 1) / L::kRows;
   p.tiles_x = tiles_x;
   const size_t lds_bytes = sizeof(double) * (size_t)L::kDoubles;
-  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, INV, GRAD>,
+  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, INV, EPI>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
-  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, INV, GRAD>), dim3((unsigned)blocks), dim3(kThreads),
+  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, INV, EPI>), dim3((unsigned)blocks), dim3(kThreads),
                      lds_bytes, s, p);
   return hipGetLastError();
 }
@@ -392,8 +398,11 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
 template <int DEG, int NT, bool INV>
 hipError_t launch_nt(const F64Params& p, hipStream_t s) {
   constexpr int R = NT <= 3 ? 4 : (NT <= 6 ? 2 : 1);
-  return p.grads ? launch_impl<DEG, NT, R, INV, true>(p, s)
-                 : launch_impl<DEG, NT, R, INV, false>(p, s);
+  if (p.rigid) {
+    if constexpr (DEG == 1 && NT == 1) return launch_impl<DEG, NT, R, INV, 2>(p, s);
+    return hipErrorInvalidValue;
+  }
+  return p.grads ? launch_impl<DEG, NT, R, INV, 1>(p, s) : launch_impl<DEG, NT, R, INV, 0>(p, s);
 }
 
 template <int DEG, bool INV>
@@ -442,6 +451,7 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   p.fields = a.fields;
   p.deg_out = a.deg_out;
   p.grads = a.grads;
+  p.rigid = a.rigid;
   if (a.wkind == 2) return launch_kind<true>(p, a.degree, nt, stream);   // inverse distance
   return launch_kind<false>(p, a.degree, nt, stream);                    // Gaussian
 }

@@ -23,6 +23,7 @@ struct FitArgs {
   uint8_t* deg_out;     // [H][W] or null
   int32_t lp_slab;      // 16-bit paths: attributes per slab, 0 = lp_slab_plan's choice
   float* grads;         // [D][2][H][W] slopes of the local fits, or null
+  bool rigid;           // rigid map of 2-vector values (degree 1 moments, D = 2)
 };
 
 // Number of basis terms m and of distinct moment monomials for a degree.

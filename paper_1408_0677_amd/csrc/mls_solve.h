@@ -235,4 +235,49 @@ __device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, do
   return (uint8_t)accepted;
 }
 
+// Rigid MLS (Eq. 9-10) of 2-vector values at one node, from the linear-basis
+// moments of the tile frame (g[0..5], then R[c * 2 + d] for c = 1, u_x, u_y).
+// With dp_i, dq_i the offsets from the weighted centroids p*, q* and
+// dv = v - p*, each term dq_i [dp_i; -dp_i^perp][dv; -dv^perp]^T of the
+// printed sum is (dq_i . dp_i) dv rotated by a quarter turn's share of
+// (dq_i x dp_i), so
+//   f'(v) = (dv_x mu + dv_y nu, -dv_x nu + dv_y mu),
+//   mu = sum w dq . dp,   nu = sum w (dq_x dp_y - dq_y dp_x),
+// and f = |dv| f' / |f'| + q* = (dv_x mu + dv_y nu, -dv_x nu + dv_y mu) / rho
+// + q*, rho = sqrt(mu^2 + nu^2).  These sums are the first moments and the
+// basis x value moments shifted to the node (u_p = u - delta), scaled by h.
+// Where rho = 0 or dv = 0 the value is q*.  Returns the degree code (1, or
+// 255 below the weight floor).
+template <typename Acc>
+__device__ __forceinline__ uint8_t rigid_node(const Acc* g, double ex, double ey, double h,
+                                              double floor_w, float* fields, int64_t plane) {
+  const double w0 = (double)g[0];
+  if (!(w0 >= floor_w)) {
+    fields[0] = __builtin_nanf("");
+    fields[plane] = __builtin_nanf("");
+    return 255;
+  }
+  const Acc* R = g + 6;
+  const double sx = (double)g[1] - ex * w0, sy = (double)g[2] - ey * w0;
+  const double q0 = (double)R[0], q1 = (double)R[1];
+  const double sxq0 = (double)R[2] - ex * q0, sxq1 = (double)R[3] - ex * q1;
+  const double syq0 = (double)R[4] - ey * q0, syq1 = (double)R[5] - ey * q1;
+  const double P0 = h * sx / w0, P1 = h * sy / w0;   // p* - v
+  const double Q0 = q0 / w0, Q1 = q1 / w0;           // q*
+  // c_ad = sum w dp_a dq_d
+  const double c00 = h * sxq0 - w0 * P0 * Q0, c01 = h * sxq1 - w0 * P0 * Q1;
+  const double c10 = h * syq0 - w0 * P1 * Q0, c11 = h * syq1 - w0 * P1 * Q1;
+  const double mu = c00 + c11, nu = c10 - c01;
+  const double d0 = -P0, d1 = -P1;                   // v - p*
+  const double rho = sqrt(mu * mu + nu * nu);
+  double f0 = Q0, f1 = Q1;
+  if (rho > 0.0 && (d0 != 0.0 || d1 != 0.0)) {
+    f0 += (d0 * mu + d1 * nu) / rho;
+    f1 += (-d0 * nu + d1 * mu) / rho;
+  }
+  fields[0] = (float)f0;
+  fields[plane] = (float)f1;
+  return 1;
+}
+
 }  // namespace mls

@@ -58,7 +58,8 @@ def _fit(lib, n=10, d=2, basis=1, kind=0, h=0.1, alpha=1.0, grid=(0.0, 0.0, 0.1,
     (dict(d=0), b"d = 0"),
     (dict(d=84), b"d = 84"),
     (dict(basis=2, d=41), b"d = 41"),
-    (dict(basis=3), b"basis 3"),
+    (dict(basis=4), b"basis 4"),
+    (dict(basis=3, d=3), b"2-vector values"),
     (dict(kind=7), b"weight kind 7"),
     (dict(h=0.0), b"h = 0"),
     (dict(h=float("nan")), b"h = nan"),
