@@ -33,11 +33,12 @@ PEAK_HBM_GBS = 8000.0
 
 
 def moment_terms(basis):
-    return {"constant": 1, "linear": 6, "quadratic": 15}[basis]
+    # the rigid map is computed from the linear-basis contraction
+    return {"constant": 1, "linear": 6, "quadratic": 15, "rigid": 6}[basis]
 
 
 def basis_terms(basis):
-    return {"constant": 1, "linear": 3, "quadratic": 6}[basis]
+    return {"constant": 1, "linear": 3, "quadratic": 6, "rigid": 3}[basis]
 
 
 def cpu_baseline(w, row_stride=1, precision_note="FP64"):
@@ -233,19 +234,35 @@ def main():
         return
 
     if args.workload == "t1":
+        import dataclasses
         recs = [fit_step_bench(args, wl.t1(n), "f64") for n in (306, 1000, 2245)]
+        # the paper's other two modes at the same shape: Mean MLS (Eq. 5, the
+        # constant basis) and Rigid MLS (Eq. 9-10)
+        quiet = argparse.Namespace(**dict(vars(args), no_cpu_baseline=True))
+        mean = [fit_step_bench(quiet, dataclasses.replace(wl.t1(n), basis="constant"), "f64")
+                for n in (306, 1000, 2245)]
+        rigid = [fit_step_bench(quiet, dataclasses.replace(wl.t1(n), basis="rigid"), "f64")
+                 for n in (306, 1000, 2245)]
         out = dict(recs[-1])
         out["metric"] = ("MLS pixel·point pairs/s at the timing-table shape (600^2, D = 2, "
                          "linear, inverse-distance weight)")
         # the paper's Affine MLS timings at this shape (Table 1, GTX 285, its
         # own shader): context for the same workload on other hardware
         paper_s = {306: 0.026670, 1000: 0.100724, 2245: 0.242192}
-        out["per_n"] = [{"points": r["config"]["points"], "ms_per_step": r["ms_per_step"],
-                         "fit_p50_ms": r["latency_ms"]["fit_p50"], "pairs_per_s": r["value"],
-                         "paper_affine_s": paper_s[r["config"]["points"]],
-                         "speedup_vs_paper_fit": paper_s[r["config"]["points"]] * 1e3
-                                                 / r["latency_ms"]["fit_p50"],
-                         "cpu_baseline": r.get("cpu_baseline")} for r in recs]
+        paper_mean_s = {306: 0.017420, 1000: 0.064938, 2245: 0.147089}
+        paper_rigid_s = {306: 0.028846, 1000: 0.116083, 2245: 0.246789}
+        out["per_n"] = []
+        for r, rm, rr in zip(recs, mean, rigid):
+            n = r["config"]["points"]
+            out["per_n"].append({
+                "points": n, "ms_per_step": r["ms_per_step"],
+                "fit_p50_ms": r["latency_ms"]["fit_p50"], "pairs_per_s": r["value"],
+                "paper_affine_s": paper_s[n],
+                "speedup_vs_paper_fit": paper_s[n] * 1e3 / r["latency_ms"]["fit_p50"],
+                "mean_fit_p50_ms": rm["latency_ms"]["fit_p50"], "paper_mean_s": paper_mean_s[n],
+                "rigid_fit_p50_ms": rr["latency_ms"]["fit_p50"],
+                "paper_rigid_s": paper_rigid_s[n],
+                "cpu_baseline": r.get("cpu_baseline")})
         # value (pairs/s of the whole step at N = 2245) over the paper's pairs/s
         out["vs_baseline"] = out["value"] / (600 * 600 * 2245 / paper_s[2245])
         print(json.dumps(out), flush=True)
