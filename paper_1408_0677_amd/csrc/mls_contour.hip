@@ -192,8 +192,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(Cont
   const float* f = p.fields + (int64_t)d * p.W * p.H;
   WaveCells w;
   load_wave_cells(p, f, chunk, lane, w);
+  // isovalues 64 at a time in one vector load, read back per iteration with
+  // a lane broadcast instead of a scalar memory load each
+  float isov = 0.0f;
   for (int k = 0; k < p.n_iso; ++k) {
-    const float iso = p.iso[d * p.n_iso + k];
+    if ((k & 63) == 0) isov = (k + lane < p.n_iso) ? p.iso[d * p.n_iso + k + lane] : 0.0f;
+    const float iso = __builtin_bit_cast(
+        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), k & 63));
     int64_t count = 0;
     if (p.cases) {
 #pragma unroll
@@ -296,8 +301,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(Conto
   WaveCells w;
   load_wave_cells(p, f, chunk, lane, w);
   const uint64_t below = (1ull << lane) - 1ull;   // lanes before this one
+  // isovalues 64 at a time in one vector load, read back per iteration with
+  // a lane broadcast instead of a scalar memory load each
+  float isov = 0.0f;
   for (int k = 0; k < p.n_iso; ++k) {
-    const float iso = p.iso[d * p.n_iso + k];
+    if ((k & 63) == 0) isov = (k + lane < p.n_iso) ? p.iso[d * p.n_iso + k + lane] : 0.0f;
+    const float iso = __builtin_bit_cast(
+        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), k & 63));
     if (!__any(iso > w.lo && iso <= w.hi)) continue;
     const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
     int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
