@@ -442,6 +442,156 @@ int oracle_rigid_grid(const float* pts, const float* vals, int64_t n, int32_t wk
 }
 
 /* ---------------------------------------------------------------------- */
+/* Planarity-preserving force-directed layout (Sec. 3.2, Eq. 1-3)          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One node's move in one iteration, from the positions at the start of the
+ * iteration (every node reads the same snapshot).  Forces, as printed:
+ *   repulsion from every other node u:   C V / (|V|^3 + eta),  V = v - u
+ *   spring along each mesh edge (v, u):  |V| log((|V| + eta) / D) (-V)
+ *   node-edge repulsion for each triangle (v, a, b) around v:
+ *                                        -C R / (|R|^2 + eta),
+ *     R the vector from v to the line through a and b (to the foot of the
+ *     perpendicular).
+ * Readings: the summed force is the move, shortened to the temperature t if
+ * it is longer; then the planarity constraint: each triangle (v, a, b) has
+ * three limiting lines, each through the midpoints of two of its edges (so
+ * parallel to the third edge and halfway between it and the opposite
+ * vertex), and v may cross none of them.  For the line parallel to ab the
+ * perpendicular from v is R / 2; for the line parallel to vb (resp. va),
+ * v lies on that edge, and the perpendicular from v is half of a's (resp.
+ * b's) offset from the line vb (resp. va).  The move's component along each
+ * such R_i may not exceed |R_i| - eta; the whole move is scaled down to the
+ * tightest bound (scaling keeps every half-plane constraint that already
+ * holds, so all hold at once).  A triangle with a zero-length edge defines
+ * no line and is skipped.
+ */
+static void layout_move(const double* x, int64_t n, int64_t v, const int32_t* adj_start,
+                        const int32_t* adj, const int32_t* fan_start, const int32_t* fan,
+                        double C, double D, double eta, double t, double* mv) {
+  const double vx = x[2 * v], vy = x[2 * v + 1];
+  double fx = 0.0, fy = 0.0;
+  for (int64_t u = 0; u < n; ++u) {
+    if (u == v) continue;
+    const double ax = vx - x[2 * u], ay = vy - x[2 * u + 1];
+    const double L = sqrt(ax * ax + ay * ay);
+    const double s = C / (L * L * L + eta);
+    fx += s * ax;
+    fy += s * ay;
+  }
+  for (int32_t k = adj_start[v]; k < adj_start[v + 1]; ++k) {
+    const int32_t u = adj[k];
+    const double ax = vx - x[2 * u], ay = vy - x[2 * u + 1];
+    const double L = sqrt(ax * ax + ay * ay);
+    const double s = L * log((L + eta) / D);
+    fx -= s * ax;
+    fy -= s * ay;
+  }
+  for (int32_t k = fan_start[v]; k < fan_start[v + 1]; ++k) {
+    const int32_t a = fan[2 * k], b = fan[2 * k + 1];
+    const double ex = x[2 * b] - x[2 * a], ey = x[2 * b + 1] - x[2 * a + 1];
+    const double e2 = ex * ex + ey * ey;
+    if (!(e2 > 0.0)) continue;
+    const double tt = ((vx - x[2 * a]) * ex + (vy - x[2 * a + 1]) * ey) / e2;
+    const double rx = x[2 * a] + tt * ex - vx, ry = x[2 * a + 1] + tt * ey - vy;
+    const double s = -C / (rx * rx + ry * ry + eta);
+    fx += s * rx;
+    fy += s * ry;
+  }
+  const double fl = sqrt(fx * fx + fy * fy);
+  if (fl > t) {
+    fx *= t / fl;
+    fy *= t / fl;
+  }
+  double scale = 1.0;
+  for (int32_t k = fan_start[v]; k < fan_start[v + 1]; ++k) {
+    /* the triangle's vertices, v first; line i is parallel to the edge
+       opposite corner i, halfway to corner i */
+    const double P[3][2] = {{vx, vy},
+                            {x[2 * fan[2 * k]], x[2 * fan[2 * k] + 1]},
+                            {x[2 * fan[2 * k + 1]], x[2 * fan[2 * k + 1] + 1]}};
+    for (int i = 0; i < 3; ++i) {
+      const double* c = P[i];
+      const double* e0 = P[(i + 1) % 3];
+      const double* e1 = P[(i + 2) % 3];
+      const double ex = e1[0] - e0[0], ey = e1[1] - e0[1];
+      const double e2 = ex * ex + ey * ey;
+      if (!(e2 > 0.0)) continue;
+      /* offset of corner i from the opposite edge's line; the limiting
+         line sits at half of it */
+      const double tt = ((c[0] - e0[0]) * ex + (c[1] - e0[1]) * ey) / e2;
+      const double ox = c[0] - (e0[0] + tt * ex), oy = c[1] - (e0[1] + tt * ey);
+      /* perpendicular from v to the limiting line: from v's own line
+         (i = 0: v is the corner, the line is half-way towards the edge;
+         i > 0: v lies on the edge's line, the line is half-way towards the
+         corner) */
+      const double rx = i == 0 ? -0.5 * ox : 0.5 * ox, ry = i == 0 ? -0.5 * oy : 0.5 * oy;
+      const double rl = sqrt(rx * rx + ry * ry);
+      if (!(rl > 0.0)) {
+        scale = 0.0;
+        continue;
+      }
+      const double proj = (fx * rx + fy * ry) / rl;
+      if (proj > 0.0) {
+        const double room = rl - eta > 0.0 ? rl - eta : 0.0;
+        if (proj * scale > room) scale = room / proj;
+      }
+    }
+  }
+  mv[0] = fx * scale;
+  mv[1] = fy * scale;
+}
+
+/*
+ * `iterations` layout iterations from pos_in[n][2] (float64), temperature
+ * t_k = t0 lambda^k in iteration k.  Mesh: CSR neighbour lists
+ * adj[adj_start[v] .. adj_start[v+1]) and triangle fans, the other two
+ * vertices (a, b) of each triangle around v at fan[2 k], fan[2 k + 1] for
+ * k in [fan_start[v], fan_start[v+1]).  Writes pos_out[n][2].
+ * Returns 0, or -1 on invalid arguments.
+ */
+int oracle_layout(const double* pos_in, int64_t n, const int32_t* adj_start,
+                  const int32_t* adj, const int32_t* fan_start, const int32_t* fan,
+                  double C, double D, double eta, double t0, double lambda,
+                  int32_t iterations, int32_t nthreads, double* pos_out) {
+  if (!pos_in || !pos_out || n < 1 || !adj_start || !fan_start || iterations < 0 ||
+      !(D > 0.0) || !(eta > 0.0) || !(t0 >= 0.0) || !(lambda > 0.0))
+    return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  double* a = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+  double* b = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+  if (!a || !b) {
+    free(a);
+    free(b);
+    return -1;
+  }
+  memcpy(a, pos_in, sizeof(double) * 2 * (size_t)n);
+  double t = t0;
+  for (int32_t it = 0; it < iterations; ++it) {
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < n; ++v) {
+      double mv[2];
+      layout_move(a, n, v, adj_start, adj, fan_start, fan, C, D, eta, t, mv);
+      b[2 * v] = a[2 * v] + mv[0];
+      b[2 * v + 1] = a[2 * v + 1] + mv[1];
+    }
+    double* tmp = a;
+    a = b;
+    b = tmp;
+    t *= lambda;
+  }
+  memcpy(pos_out, a, sizeof(double) * 2 * (size_t)n);
+  free(a);
+  free(b);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Marching squares                                                        */
 /* ---------------------------------------------------------------------- */
 

@@ -67,6 +67,8 @@ def _load():
     lib.oracle_rigid_grid.argtypes = [P, P, i64, i32, f64, f64, f64, f64, f64, f64, i32, i32,
                                       P, i64, f64, i32, P, P]
     lib.oracle_rigid_grid.restype = ctypes.c_int
+    lib.oracle_layout.argtypes = [P, i64, P, P, P, P, f64, f64, f64, f64, f64, i32, i32, P]
+    lib.oracle_layout.restype = ctypes.c_int
     for name in ("oracle_contour_f64", "oracle_contour_f32"):
         fn = getattr(lib, name)
         fn.argtypes = [P, i32, i32, f64, f64, f64, f64, P, i32, i32, P, P, P, i64]
@@ -177,6 +179,24 @@ def rigid_grid(points, values, grid, weight="invpow", h=0.05, alpha=1.0,
     if pixels is None:
         return fields.reshape(2, H, W), deg.reshape(H, W)
     return fields, deg
+
+
+def layout(pos, mesh, C, D, eta, t0, lam, iterations, threads=0):
+    """Planarity-preserving layout iterations (Sec. 3.2, Eq. 1-3) from
+    positions (n, 2) on a mesh given as a dict of int32 arrays adj_start,
+    adj, fan_start, fan (see mesh_arrays).  Returns the positions (n, 2)
+    after `iterations` iterations, float64."""
+    x = np.ascontiguousarray(pos, dtype=np.float64)
+    n = x.shape[0]
+    arrs = [np.ascontiguousarray(mesh[k], dtype=np.int32)
+            for k in ("adj_start", "adj", "fan_start", "fan")]
+    out = np.empty_like(x)
+    rc = _load().oracle_layout(_ptr(x), n, *[_ptr(a) for a in arrs], float(C), float(D),
+                               float(eta), float(t0), float(lam), int(iterations), int(threads),
+                               _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_layout rejected its arguments")
+    return out
 
 
 def contour(fields, grid, iso, f32=False):

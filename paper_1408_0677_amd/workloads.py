@@ -198,6 +198,45 @@ def t1(n, seed=0):
                     "fp64", n_iso=10, alpha=1.0)
 
 
+def mesh_arrays(points):
+    """Delaunay triangulation of (N, 2) points (the paper's upstream step,
+    done here on the host with scipy) as the layout's inputs: CSR
+    neighbour lists (adj_start[N+1], adj) and triangle fans (fan_start[N+1],
+    fan[2 T_v]: the other two vertices of each triangle around a node), all
+    int32, plus the triangles (T, 3)."""
+    from scipy.spatial import Delaunay
+    pts = np.asarray(points, dtype=np.float64)
+    n = pts.shape[0]
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    nb = [set() for _ in range(n)]
+    fans = [[] for _ in range(n)]
+    for a, b, c in tri:
+        nb[a].update((b, c)); nb[b].update((a, c)); nb[c].update((a, b))
+        fans[a].append((b, c)); fans[b].append((c, a)); fans[c].append((a, b))
+    adj_start = np.zeros(n + 1, np.int32)
+    adj_start[1:] = np.cumsum([len(x) for x in nb])
+    adj = np.array([u for x in nb for u in sorted(x)], np.int32)
+    fan_start = np.zeros(n + 1, np.int32)
+    fan_start[1:] = np.cumsum([len(x) for x in fans])
+    fan = np.array([v for x in fans for pr in x for v in pr], np.int32)
+    return {"adj_start": adj_start, "adj": adj, "fan_start": fan_start, "fan": fan,
+            "triangles": tri.astype(np.int32)}
+
+
+def layout_workload(n, seed=0, canvas=600.0):
+    """Timing-table layout shape: n uniform points on a canvas x canvas
+    square, their Delaunay mesh, and parameters in canvas units: D the mean
+    edge length, C = D^3 (repulsion of about D at distance D), eta = 1e-3 D,
+    t0 = D / 4, lambda = 0.995."""
+    rng = np.random.default_rng(seed + n)
+    pts = rng.random((n, 2)) * canvas
+    mesh = mesh_arrays(pts)
+    src = np.repeat(np.arange(n), np.diff(mesh["adj_start"]))
+    D = float(np.linalg.norm(pts[src] - pts[mesh["adj"]], axis=1).mean())
+    params = {"C": D ** 3, "D": D, "eta": 1e-3 * D, "t0": 0.25 * D, "lam": 0.995}
+    return pts, mesh, params
+
+
 def c4_requests(seed=0, count=256):
     """Request mix of the served form: sizes, bases and bandwidths drawn at
     random; the bandwidth puts about 20 (linear) or 40 (quadratic) points

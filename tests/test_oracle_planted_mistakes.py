@@ -51,10 +51,18 @@ MUTATIONS = [
      "out[0] = fr[0] / nf + qs[0];"),
     ("rigid centroid dropped", "out[out_stride] = nv * fr[1] / nf + qs[1];",
      "out[out_stride] = nv * fr[1] / nf;"),
+    ("layout clamps only the corner's own line", "for (int i = 0; i < 3; ++i) {",
+     "for (int i = 0; i < 1; ++i) {"),
+    ("layout spring pushes instead of pulling", "    fx -= s * ax;\n    fy -= s * ay;",
+     "    fx += s * ax;\n    fy += s * ay;"),
+    ("layout temperature ignored", "  if (fl > t) {", "  if (fl > 1e300) {"),
+    ("layout node-edge force reversed", "const double s = -C / (rx * rx + ry * ry + eta);",
+     "const double s = C / (rx * rx + ry * ry + eta);"),
 ]
 
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_contour_pins.py",
-             "tests/test_oracle_grad_pins.py", "tests/test_oracle_rigid_pins.py"]
+             "tests/test_oracle_grad_pins.py", "tests/test_oracle_rigid_pins.py",
+             "tests/test_oracle_layout_pins.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
