@@ -212,6 +212,41 @@ mls_status mls_fit_grad(mls_context* ctx, const float* d_points, const float* d_
                         const mls_solve_opts* opts, float* d_fields, float* d_grad,
                         uint8_t* d_degree, void* stream);
 
+/* Parameters of the planarity-preserving layout (Sec. 3.2, Eq. 1-3). */
+typedef struct {
+  double C;       /* repulsion scale (Eq. 1 and 3), >= 0 */
+  double D;       /* desired edge length (Eq. 2), > 0 */
+  double eta;     /* softening of Eq. 1-3, and the margin every node keeps
+                     from every limiting line, > 0 */
+  double t0;      /* temperature of the first iteration: the longest move */
+  double lambda;  /* temperature decay, t_k = t0 lambda^k, 0 < lambda <= 1 */
+} mls_layout_params;
+
+/*
+ * Planarity-preserving force-directed layout of a triangulated point set
+ * (Sec. 3.2, Eq. 1-3, with the limiting-line constraint): `iterations`
+ * iterations; in each, every node moves by the sum of the repulsion from
+ * every other node, the springs along its mesh edges and the repulsion from
+ * the opposite edge of each of its triangles, shortened to the
+ * temperature, then scaled down so that it crosses none of the three
+ * limiting lines (through the midpoints of two edges) of any of its
+ * triangles, keeping eta clear.  No triangle of the mesh can flip.
+ *  d_pos        float32 [n][2] positions, device; read, then overwritten
+ *               with the result
+ *  d_adj_start  int32 [n + 1] CSR starts of the neighbour lists, device
+ *  d_adj        int32 [n_adj] neighbour indices, device (NULL if n_adj = 0)
+ *  d_fan_start  int32 [n + 1] starts of the triangle fans, device
+ *  d_fan        int32 [n_fan][2] the other two vertices of each triangle
+ *               around the node, device (NULL if n_fan = 0)
+ * Entries outside [0, n) and list ranges outside the arrays are ignored,
+ * not read.  The state is float64 in library scratch (32 n bytes).  Runs on
+ * the stream; returns after enqueueing.
+ */
+mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* d_adj_start,
+                      const int32_t* d_adj, int64_t n_adj, const int32_t* d_fan_start,
+                      const int32_t* d_fan, int64_t n_fan, const mls_layout_params* params,
+                      int32_t iterations, void* stream);
+
 /*
  * Device scratch bytes mls_fit needs for this request (0 for MLS_PREC_F64);
  * 0 also for invalid arguments.

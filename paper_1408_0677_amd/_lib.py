@@ -19,7 +19,7 @@ EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_context_reserve", "mls_server_create", "mls_server_destroy",
            "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
            "mls_server_poll", "mls_server_wait", "mls_server_last_error",
-           "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad")
+           "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad", "mls_layout")
 
 
 class MlsGrid(ctypes.Structure):
@@ -36,6 +36,11 @@ class MlsWeight(ctypes.Structure):
 class MlsSolveOpts(ctypes.Structure):
     _fields_ = [("pivot_tol", ctypes.c_double), ("weight_floor", ctypes.c_double),
                 ("lp_terms", ctypes.c_int32), ("lp_slab", ctypes.c_int32)]
+
+
+class MlsLayoutParams(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_double), ("D", ctypes.c_double), ("eta", ctypes.c_double),
+                ("t0", ctypes.c_double), ("lam", ctypes.c_double)]
 
 
 class MlsRequest(ctypes.Structure):
@@ -81,6 +86,9 @@ def load():
                                  ctypes.POINTER(MlsGrid), i32, ctypes.POINTER(MlsSolveOpts),
                                  P, P, P, P]
     lib.mls_fit_grad.restype = ctypes.c_int
+    lib.mls_layout.argtypes = [P, P, i64, P, P, i64, P, P, i64,
+                               ctypes.POINTER(MlsLayoutParams), i32, P]
+    lib.mls_layout.restype = ctypes.c_int
     lib.mls_contour.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P, i64,
                                 ctypes.POINTER(i64), P]
     lib.mls_contour.restype = ctypes.c_int

@@ -149,6 +149,27 @@ def fit_grad(points, values, grid: dict, basis: str = "linear", weight: str = "g
     return out, grads, degree
 
 
+def layout(pos, mesh: dict, C: float, D: float, eta: float, t0: float, lam: float,
+           iterations: int, ctx: Context | None = None, stream=None):
+    """Planarity-preserving layout (mls_layout).  ``pos`` float32 (n, 2)
+    device tensor, updated in place and returned; ``mesh`` holds int32 device
+    tensors adj_start (n+1), adj, fan_start (n+1), fan (T, 2) or flat."""
+    import torch
+    assert pos.dtype == torch.float32 and pos.is_contiguous()
+    n = pos.shape[0]
+    adj, fan = mesh["adj"], mesh["fan"]
+    n_adj = int(adj.numel())
+    n_fan = int(fan.numel()) // 2
+    ctx = ctx or default_context(pos.device.index)
+    prm = _lib.MlsLayoutParams(float(C), float(D), float(eta), float(t0), float(lam))
+    st = _lib.load().mls_layout(ctx.handle, _ptr(pos), n, _ptr(mesh["adj_start"]),
+                                _ptr(adj) if n_adj else None, n_adj, _ptr(mesh["fan_start"]),
+                                _ptr(fan) if n_fan else None, n_fan, ctypes.byref(prm),
+                                int(iterations), _stream_handle(stream))
+    _check(st, "mls_layout")
+    return pos
+
+
 CAPACITY_ERROR = -3
 
 

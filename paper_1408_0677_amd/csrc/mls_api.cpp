@@ -443,6 +443,59 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   return MLS_OK;
 }
 
+mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* d_adj_start,
+                      const int32_t* d_adj, int64_t n_adj, const int32_t* d_fan_start,
+                      const int32_t* d_fan, int64_t n_fan, const mls_layout_params* params,
+                      int32_t iterations, void* stream) {
+  g_last_error[0] = '\0';
+  if (n < 1 || n > ((int64_t)1 << 30))
+    return fail(MLS_ERR_INVALID_ARG, "n = %lld; need 1 .. 2^30 nodes", (long long)n);
+  if (n_adj < 0 || n_fan < 0 || n_adj > ((int64_t)1 << 31) || n_fan > ((int64_t)1 << 30))
+    return fail(MLS_ERR_INVALID_ARG, "n_adj = %lld, n_fan = %lld", (long long)n_adj,
+                (long long)n_fan);
+  if (iterations < 0) return fail(MLS_ERR_INVALID_ARG, "iterations = %d", iterations);
+  if (!params) return fail(MLS_ERR_INVALID_ARG, "params is NULL");
+  const mls_layout_params& q = *params;
+  if (!is_finite(q.C) || !(q.C >= 0.0) || !is_finite(q.D) || !(q.D > 0.0) ||
+      !is_finite(q.eta) || !(q.eta > 0.0) || !is_finite(q.t0) || !(q.t0 >= 0.0) ||
+      !is_finite(q.lambda) || !(q.lambda > 0.0) || !(q.lambda <= 1.0))
+    return fail(MLS_ERR_INVALID_ARG, "layout parameters: need C >= 0, D > 0, eta > 0, t0 >= 0, "
+                "0 < lambda <= 1, all finite");
+  if (!d_pos || !d_adj_start || !d_fan_start || (n_adj > 0 && !d_adj) || (n_fan > 0 && !d_fan))
+    return fail(MLS_ERR_INVALID_ARG, "a required device array is NULL");
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  mls_status st;
+  if ((st = check_device_ptr(ctx, d_pos, "d_pos")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_adj_start, "d_adj_start")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_fan_start, "d_fan_start")) != MLS_OK) return st;
+  if (n_adj > 0 && (st = check_device_ptr(ctx, d_adj, "d_adj")) != MLS_OK) return st;
+  if (n_fan > 0 && (st = check_device_ptr(ctx, d_fan, "d_fan")) != MLS_OK) return st;
+  const size_t half = align_up(sizeof(double) * 2 * (size_t)n, 256);
+  if ((st = ensure_scratch(ctx->fit_scratch, 2 * half)) != MLS_OK) return st;
+  mls::LayoutArgs a;
+  a.pos = d_pos;
+  a.n = n;
+  a.adj_start = d_adj_start;
+  a.adj = d_adj;
+  a.n_adj = n_adj;
+  a.fan_start = d_fan_start;
+  a.fan = d_fan;
+  a.n_fan = n_fan;
+  a.C = q.C;
+  a.D = q.D;
+  a.eta = q.eta;
+  a.t0 = q.t0;
+  a.lambda = q.lambda;
+  a.iterations = iterations;
+  a.buf0 = (double*)ctx->fit_scratch.ptr;
+  a.buf1 = (double*)((char*)ctx->fit_scratch.ptr + half);
+  e = mls::launch_layout(a, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "layout kernel launch");
+  return MLS_OK;
+}
+
 mls_status mls_context_reserve(mls_context* ctx, size_t bytes) {
   g_last_error[0] = '\0';
   if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");

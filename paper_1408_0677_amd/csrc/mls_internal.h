@@ -184,4 +184,17 @@ int64_t contour_scratch_entries(int32_t D, int32_t n_iso, int32_t W, int32_t H);
 int64_t contour_scan_tiles(int64_t entries);
 hipError_t launch_contour(const ContourArgs& a, hipStream_t stream);
 
+// Planarity-preserving layout iterations (float64 state in buf0/buf1,
+// each [n][2]); pos holds the float32 positions in and out.
+struct LayoutArgs {
+  float* pos;
+  int64_t n;
+  const int32_t *adj_start, *adj, *fan_start, *fan;
+  int64_t n_adj, n_fan;
+  double C, D, eta, t0, lambda;
+  int32_t iterations;
+  double *buf0, *buf1;
+};
+hipError_t launch_layout(const LayoutArgs& a, hipStream_t s);
+
 }  // namespace mls

@@ -155,3 +155,30 @@ def test_server_arguments_rejected_without_device(lib):
     assert lib.mls_server_tuned_classes(None) == 0
     assert lib.mls_status_string(-5) == b"MLS_ERR_OVER_BUDGET"
     assert lib.mls_status_string(1) == b"MLS_PENDING"
+
+
+def _layout(lib, n=10, n_adj=4, n_fan=2, prm=(1.0, 0.1, 1e-4, 0.01, 0.99), iters=5,
+            pos=1, starts=1, arrays=1, ctx=None):
+    from paper_1408_0677_amd import _lib
+    fake = ctypes.c_void_p(0x1000)
+    p = None if prm is None else ctypes.byref(_lib.MlsLayoutParams(*prm))
+    return lib.mls_layout(ctx, fake if pos else None, n, fake if starts else None,
+                          fake if arrays else None, n_adj, fake if starts else None,
+                          fake if arrays else None, n_fan, p, iters, None)
+
+
+@pytest.mark.parametrize("kwargs,needle", [
+    (dict(n=0), b"n = 0"),
+    (dict(n_adj=-1), b"n_adj"),
+    (dict(iters=-2), b"iterations"),
+    (dict(prm=None), b"params is NULL"),
+    (dict(prm=(1.0, 0.1, 0.0, 0.01, 0.99)), b"layout parameters"),
+    (dict(prm=(1.0, 0.1, 1e-4, 0.01, 1.5)), b"layout parameters"),
+    (dict(prm=(1.0, -0.1, 1e-4, 0.01, 0.9)), b"layout parameters"),
+    (dict(pos=0), b"required device array"),
+    (dict(arrays=0), b"required device array"),
+    (dict(), b"ctx is NULL"),
+])
+def test_layout_arguments_rejected_before_device(lib, kwargs, needle):
+    assert _layout(lib, **kwargs) == -1
+    assert needle in lib.mls_last_error(), lib.mls_last_error()

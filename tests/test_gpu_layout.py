@@ -1,0 +1,95 @@
+"""GPU parity of the planarity-preserving layout (mls_layout, Sec. 3.2
+Eq. 1-3) against the oracle's iteration, and the planarity guarantee on a
+long hot run.  Positions are float32 at the boundary (float64 inside); the
+bound is 2e-6 of the point cloud's extent after 1 and 25 iterations."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def to_dev(torch, mesh):
+    return {k: torch.from_numpy(np.ascontiguousarray(mesh[k])).cuda()
+            for k in ("adj_start", "adj", "fan_start", "fan")}
+
+
+def signed_areas(x, tri):
+    a, b, c = x[tri[:, 0]], x[tri[:, 1]], x[tri[:, 2]]
+    return (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+
+
+def params_for(pts, mesh):
+    src = np.repeat(np.arange(pts.shape[0]), np.diff(mesh["adj_start"]))
+    D = float(np.linalg.norm(pts[src] - pts[mesh["adj"]], axis=1).mean())
+    return dict(C=D ** 3, D=D, eta=1e-3 * D, t0=0.25 * D, lam=0.99)
+
+
+@pytest.mark.parametrize("iters", [1, 25])
+def test_layout_matches_oracle(torch_dev, oracle, iters):
+    from paper_1408_0677_amd import api, workloads as wl
+    note(f"case layout parity {iters} iterations")
+    rng = np.random.default_rng(iters)
+    pts = rng.random((300, 2)).astype(np.float32)
+    mesh = wl.mesh_arrays(pts)
+    prm = params_for(pts.astype(np.float64), mesh)
+    P = torch_dev.from_numpy(pts.copy()).cuda()
+    api.layout(P, to_dev(torch_dev, mesh), iterations=iters, **prm)
+    torch_dev.cuda.synchronize()
+    got = P.cpu().numpy().astype(np.float64)
+    ref = oracle.layout(pts.astype(np.float64), mesh, iterations=iters, **prm)
+    err = np.abs(got - ref).max()
+    note(f"max position error {err:.3e}, moved {np.abs(ref - pts).max():.3e}")
+    assert np.abs(ref - pts).max() > 1e-4
+    assert err <= 2e-6
+
+
+def test_layout_keeps_planarity(torch_dev):
+    from paper_1408_0677_amd import api, workloads as wl
+    note("case layout planarity 2000 points x 300 iterations")
+    rng = np.random.default_rng(11)
+    pts = rng.random((2000, 2)).astype(np.float32)
+    mesh = wl.mesh_arrays(pts)
+    prm = params_for(pts.astype(np.float64), mesh)
+    prm["t0"] = prm["D"]            # hot start
+    P = torch_dev.from_numpy(pts.copy()).cuda()
+    api.layout(P, to_dev(torch_dev, mesh), iterations=300, **prm)
+    torch_dev.cuda.synchronize()
+    out = P.cpu().numpy().astype(np.float64)
+    tri = mesh["triangles"]
+    s0 = np.sign(signed_areas(pts.astype(np.float64), tri))
+    s1 = np.sign(signed_areas(out, tri))
+    assert np.all(np.isfinite(out))
+    assert np.all(s0 == s1)
+    assert np.abs(out - pts).max() > 1e-3
+
+
+def test_layout_ignores_malformed_lists(torch_dev):
+    """Indices outside [0, n) and ranges past the arrays are skipped."""
+    import torch
+    from paper_1408_0677_amd import api
+    note("case layout malformed lists")
+    n = 50
+    pts = torch.rand(n, 2, device="cuda")
+    adj_start = torch.tensor([0] + [3] * (n - 1) + [10_000], dtype=torch.int32, device="cuda")
+    adj = torch.tensor([1, -5, 99999], dtype=torch.int32, device="cuda")
+    fan_start = torch.tensor([-7] + [1] * n, dtype=torch.int32, device="cuda")
+    fan = torch.tensor([[2, 70000]], dtype=torch.int32, device="cuda")
+    api.layout(pts, {"adj_start": adj_start, "adj": adj, "fan_start": fan_start, "fan": fan},
+               C=1e-3, D=0.1, eta=1e-4, t0=0.01, lam=0.9, iterations=3)
+    torch.cuda.synchronize()
+    assert torch.isfinite(pts).all()
