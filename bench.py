@@ -203,6 +203,96 @@ def serve_bench(args):
     return out
 
 
+LAYOUT_ITERS = 1000
+# fp64 operations of one ordered source-node pair of the repulsion (Eq. 1):
+# two differences, two squares and their sum, sqrt, two products for the
+# cube, +eta, the division, two products and two accumulations
+LAYOUT_OPS_PER_PAIR = 15
+# one fp64 add or multiply per lane per clock: 256 CUs x 64 lanes x 2.4 GHz
+FP64_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+
+
+def layout_bench(args):
+    """Layout runs of LAYOUT_ITERS iterations (t_k = t0 lambda^k) on the
+    Delaunay meshes of the timing-table sizes, plus a 65536-node run that
+    fills the chip; positions resident in HBM, timed with events on the
+    stream the iterations are launched on."""
+    import torch
+    from paper_1408_0677_amd import api, workloads as wl
+    paper_s = {306: 0.783082, 1000: 1.314509, 2245: 1.777599}
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n, iters in ((306, LAYOUT_ITERS), (1000, LAYOUT_ITERS), (2245, LAYOUT_ITERS),
+                     (65536, 50)):
+        pts, mesh, prm = wl.layout_workload(n)
+        P0 = torch.from_numpy(pts.astype(np.float32)).cuda()
+        M = {k: torch.from_numpy(np.ascontiguousarray(mesh[k])).cuda()
+             for k in ("adj_start", "adj", "fan_start", "fan")}
+        P = P0.clone()
+
+        def run(k):
+            P.copy_(P0)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            api.layout(P, M, iterations=k, **prm)
+            b.record(stream)
+            b.synchronize()
+            return a.elapsed_time(b)
+
+        for _ in range(max(args.warmup, 1)):
+            run(iters)
+        steps = max(args.steps // 4, 3)
+        full = [run(iters) for _ in range(steps)]
+        empty = [run(0) for _ in range(steps)]
+        per_it_us = (np.median(full) - np.median(empty)) * 1e3 / iters
+        ops = LAYOUT_OPS_PER_PAIR * n * (n - 1)
+        row = {"nodes": n, "triangles": int(mesh["triangles"].shape[0]), "iterations": iters,
+               "run_ms_p50": float(np.median(full)), "run_ms_p99": float(np.percentile(full, 99)),
+               "us_per_iteration": float(per_it_us),
+               "iterations_per_s": 1e6 / per_it_us,
+               "repulsion_ops_per_s": ops / (per_it_us * 1e-6)}
+        if n in paper_s:
+            row["paper_layout_s"] = paper_s[n]
+        rows.append(row)
+        note = f"layout n={n}: {per_it_us:.2f} us/iteration"
+        print(note, file=sys.stderr, flush=True)
+    main_row = rows[2]
+    big = rows[3]
+    achieved = big["repulsion_ops_per_s"] / 1e12
+    peak = FP64_LANE_OPS_PEAK / 1e12
+    out = {
+        "metric": "layout iterations/s (2245-node Delaunay mesh, Eq. 1-3 with the "
+                  "limiting-line clamp, float64)",
+        "value": main_row["iterations_per_s"], "unit": "iterations/s", "n_gpus": 1,
+        "steps": max(args.steps // 4, 3), "warmup": max(args.warmup, 1),
+        "ms_per_step": main_row["run_ms_p50"], "higher_is_better": True, "scaling": "weak",
+        # the paper states no iteration count for its layout times
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "layout_2245_nodes_1000_iterations", "canvas": 600,
+                   "nodes": 2245, "iterations": LAYOUT_ITERS},
+        "per_n": rows,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "Tops/s (fp64 lane operations)", "frac": achieved / peak,
+                     "traffic": None, "kernel": "layout_step_kernel<16> at 65536 nodes",
+                     "algorithmic_ops_per_launch": LAYOUT_OPS_PER_PAIR * 65536 * 65535,
+                     "kernel_us": big["us_per_iteration"]},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        pts, mesh, prm = wl.layout_workload(2245)
+        threads = min(os.cpu_count() or 1, 16)
+        k = 10000
+        t0 = time.perf_counter()
+        oracle.layout(pts.astype(np.float32).astype(np.float64), mesh, iterations=k,
+                      threads=threads, **prm)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": k / dt, "unit": "iterations/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{k} iterations of the 2245-node layout, {dt:.2f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,13 +300,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "t1"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "c4", "c5", "t1", "layout"],
                     help="c2: the 1024^2 float64 fit + contour step (default); c3: the "
                          "2048^2 / D = 64 quadratic bfloat16 fit; c5: the 4096^2 / "
                          "N = 10^6 Wendland bfloat16 fit + contour; c4: the served "
                          "request mix with Poisson arrivals; t1: the paper's timing-table "
                          "shape (600^2, N = 306 / 1000 / 2245, D = 2, linear, the "
-                         "inverse-distance weight of Eq. 4), float64")
+                         "inverse-distance weight of Eq. 4), float64; layout: the "
+                         "planarity-preserving layout of Sec. 3.2 at the timing-table "
+                         "sizes, float64")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -231,6 +324,10 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(serve_bench(args)), flush=True)
+        return
+
+    if args.workload == "layout":
+        print(json.dumps(layout_bench(args)), flush=True)
         return
 
     if args.workload == "t1":

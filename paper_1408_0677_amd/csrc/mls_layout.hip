@@ -13,12 +13,19 @@
 // at once, which is what lets every node move in parallel.
 //
 // Parallel form: nodes read the positions at the start of the iteration
-// (ping-pong buffers, float64).  A workgroup of four waves owns 64 nodes,
-// one per lane; the all-pairs repulsion is split over the four waves by
-// source (source tiles staged through LDS) and the four partial sums are
-// added in a fixed order, so results do not depend on scheduling.  The
-// exact all-pairs sum replaces the paper's kd-tree far field: at the sizes
-// the paper lays out (a few thousand points) it costs microseconds.
+// (ping-pong buffers, float64).  A workgroup of 256 lanes owns NB nodes and
+// gives each SP = 256 / NB adjacent lanes of one wave; the lanes of a node
+// split its all-pairs repulsion by source and its spring and node-edge terms
+// by list entry, then add their partial forces with an xor butterfly (every
+// lane ends with the same bits, and the order does not depend on
+// scheduling).  NB falls as n falls so that the paper's sizes (a few
+// thousand nodes) still fill the chip.  Sources are staged into LDS in
+// tiles, the next tile's loads in flight while the current one is used; the
+// list ranges, each lane's first spring and triangle and the first tile are
+// all requested before any of them is waited on.  The same lanes then share the node's triangles
+// for the limiting-line test and take the minimum of their step scales.
+// The exact all-pairs sum replaces the paper's kd-tree far field: at the
+// sizes the paper lays out it costs microseconds.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -28,9 +35,7 @@
 namespace mls {
 namespace {
 
-constexpr int kNodes = 64;      // nodes per workgroup (one per lane)
-constexpr int kWaves = 4;       // source splits
-constexpr int kTile = 256;      // sources staged per round
+constexpr int kLanes = 256;     // lanes per workgroup
 
 struct LayoutParams {
   const double* x;              // [n][2] positions at the start of the iteration
@@ -56,106 +61,227 @@ __device__ __forceinline__ void csr_range(const int32_t* start, int64_t v, int64
   *k1 = b;
 }
 
-__global__ __launch_bounds__(kNodes * kWaves) void layout_step_kernel(LayoutParams p) {
+__device__ __forceinline__ double2 load_pos(const double* x, int64_t u) {
+  return *reinterpret_cast<const double2*>(x + 2 * u);
+}
+
+// Spring of Eq. 2 on v from the neighbour at (ux, uy), added to (fx, fy).
+__device__ __forceinline__ void add_spring(double vx, double vy, double ux, double uy,
+                                           double D, double eta, double& fx, double& fy) {
 #pragma clang fp contract(off)
-  __shared__ double src[kTile][2];
-  __shared__ double part[kWaves][kNodes][2];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t v = (int64_t)blockIdx.x * kNodes + lane;
-  const bool live = v < p.n;
-  const double vx = live ? p.x[2 * v] : 0.0, vy = live ? p.x[2 * v + 1] : 0.0;
-  // repulsion: wave w takes the sources s = w, w + 4, ... of each tile
-  double fx = 0.0, fy = 0.0;
-  for (int64_t base = 0; base < p.n; base += kTile) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kTile; e += kNodes * kWaves) {
-      const int64_t u = base + e;
-      src[e][0] = u < p.n ? p.x[2 * u] : 0.0;
-      src[e][1] = u < p.n ? p.x[2 * u + 1] : 0.0;
-    }
-    __syncthreads();
-    const int cnt = (int)((p.n - base) < kTile ? (p.n - base) : kTile);
-    for (int e = wave; e < cnt; e += kWaves) {
-      if (base + e == v) continue;
-      const double ax = vx - src[e][0], ay = vy - src[e][1];
-      const double L = sqrt(ax * ax + ay * ay);
-      const double s = p.C / (L * L * L + p.eta);
-      fx += s * ax;
-      fy += s * ay;
-    }
-  }
-  part[wave][lane][0] = fx;
-  part[wave][lane][1] = fy;
-  __syncthreads();
-  if (wave != 0 || !live) return;
-  fx = ((part[0][lane][0] + part[1][lane][0]) + part[2][lane][0]) + part[3][lane][0];
-  fy = ((part[0][lane][1] + part[1][lane][1]) + part[2][lane][1]) + part[3][lane][1];
-  // springs along the mesh edges
-  int64_t k0, k1;
-  csr_range(p.adj_start, v, p.n_adj, &k0, &k1);
-  for (int64_t k = k0; k < k1; ++k) {
-    const int32_t u = p.adj[k];
-    if (u < 0 || u >= p.n) continue;
-    const double ax = vx - p.x[2 * u], ay = vy - p.x[2 * u + 1];
-    const double L = sqrt(ax * ax + ay * ay);
-    const double s = L * log((L + p.eta) / p.D);
-    fx -= s * ax;
-    fy -= s * ay;
-  }
-  // node-edge repulsion from the opposite edge of each incident triangle
-  csr_range(p.fan_start, v, p.n_fan, &k0, &k1);
-  for (int64_t k = k0; k < k1; ++k) {
-    const int32_t a = p.fan[2 * k], b = p.fan[2 * k + 1];
-    if (a < 0 || a >= p.n || b < 0 || b >= p.n) continue;
-    const double ax0 = p.x[2 * a], ay0 = p.x[2 * a + 1];
-    const double ex = p.x[2 * b] - ax0, ey = p.x[2 * b + 1] - ay0;
+  const double ax = vx - ux, ay = vy - uy;
+  const double L = sqrt(ax * ax + ay * ay);
+  const double q = L * log((L + eta) / D);
+  fx -= q * ax;
+  fy -= q * ay;
+}
+
+// Node-edge repulsion of Eq. 3 on v from the edge (a, b), added to (fx, fy).
+__device__ __forceinline__ void add_edge(double vx, double vy, double ax0, double ay0,
+                                         double bx, double by, double C, double eta, double& fx,
+                                         double& fy) {
+#pragma clang fp contract(off)
+  const double ex = bx - ax0, ey = by - ay0;
+  const double e2 = ex * ex + ey * ey;
+  if (!(e2 > 0.0)) return;
+  const double tt = ((vx - ax0) * ex + (vy - ay0) * ey) / e2;
+  const double rx = ax0 + tt * ex - vx, ry = ay0 + tt * ey - vy;
+  const double q = -C / (rx * rx + ry * ry + eta);
+  fx += q * rx;
+  fy += q * ry;
+}
+
+// Largest fraction of the move (fx, fy) that keeps node v (corner 0 of the
+// triangle v, a, b) eta clear of the triangle's three limiting lines.
+// Corner i's line lies halfway between corner i and the opposite edge; the
+// offset from v to it is half of -(v's offset from its opposite edge) for
+// i = 0 and half of corner i's offset from the edge through v for i = 1, 2.
+__device__ __forceinline__ double triangle_scale(double vx, double vy, double ax, double ay,
+                                                 double bx, double by, double fx, double fy,
+                                                 double eta) {
+#pragma clang fp contract(off)
+  const double P[3][2] = {{vx, vy}, {ax, ay}, {bx, by}};
+  double scale = 1.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double* c = P[i];
+    const double* e0 = P[(i + 1) % 3];
+    const double* e1 = P[(i + 2) % 3];
+    const double ex = e1[0] - e0[0], ey = e1[1] - e0[1];
     const double e2 = ex * ex + ey * ey;
     if (!(e2 > 0.0)) continue;
-    const double tt = ((vx - ax0) * ex + (vy - ay0) * ey) / e2;
-    const double rx = ax0 + tt * ex - vx, ry = ay0 + tt * ey - vy;
-    const double s = -p.C / (rx * rx + ry * ry + p.eta);
-    fx += s * rx;
-    fy += s * ry;
+    const double tt = ((c[0] - e0[0]) * ex + (c[1] - e0[1]) * ey) / e2;
+    const double ox = c[0] - (e0[0] + tt * ex), oy = c[1] - (e0[1] + tt * ey);
+    const double rx = i == 0 ? -0.5 * ox : 0.5 * ox, ry = i == 0 ? -0.5 * oy : 0.5 * oy;
+    const double rl = sqrt(rx * rx + ry * ry);
+    if (!(rl > 0.0)) {
+      scale = 0.0;
+      continue;
+    }
+    const double proj = (fx * rx + fy * ry) / rl;
+    if (proj > 0.0) {
+      const double room = rl - eta > 0.0 ? rl - eta : 0.0;
+      const double lim = room / proj;
+      scale = lim < scale ? lim : scale;
+    }
   }
+  return scale;
+}
+
+// C / (|V|^3 + eta) for |V|^2 = r2, the factor of V in the repulsion of
+// Eq. 1.  |V| comes from the hardware reciprocal square root and the
+// quotient from the hardware reciprocal (each an estimate good to about 23
+// bits), refined by two Newton steps and a final residual step: within a
+// few ulp of the correctly rounded value, in about half the instructions of
+// the IEEE square root and division, and without a branch.  V = 0 (the node
+// itself, or a coincident node) takes |V| = 1 so that the factor stays
+// finite and its product with V is exactly zero.
+__device__ __forceinline__ double repulsion_factor(double r2, double C, double eta) {
+  const double a = r2 > 0.0 ? r2 : 1.0;
+  double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {             // y <- y (3 - a y^2) / 2
+    const double e = fma(-(a * y), 0.5 * y, 0.5);
+    y = fma(y, e, y);
+  }
+  const double L = a * y;
+  const double den = a * L + eta;
+  double r = __builtin_amdgcn_rcp(den);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {             // r <- r (2 - den r)
+    const double e = fma(-den, r, 1.0);
+    r = fma(r, e, r);
+  }
+  const double q = C * r;
+  return fma(fma(-den, q, C), r, q);
+}
+
+template <int SP>
+__device__ __forceinline__ double group_sum(double a) {
+#pragma unroll
+  for (int w = 1; w < SP; w *= 2) a = a + __shfl_xor(a, w, SP);
+  return a;
+}
+
+template <int SP>
+__device__ __forceinline__ double group_min(double a) {
+#pragma unroll
+  for (int w = 1; w < SP; w *= 2) {
+    const double o = __shfl_xor(a, w, SP);
+    a = o < a ? o : a;
+  }
+  return a;
+}
+
+// NB nodes per workgroup; TILE sources staged into LDS per round.
+template <int NB, int TILE>
+__global__ __launch_bounds__(kLanes) void layout_step_kernel(LayoutParams p) {
+#pragma clang fp contract(off)
+  constexpr int SP = kLanes / NB;         // lanes per node, within one wave
+  constexpr int PER = TILE / kLanes;      // sources each lane stages per round
+  static_assert(SP <= 64 && TILE % kLanes == 0, "node groups must sit inside a wave");
+  __shared__ double2 src[TILE];
+  const int t = threadIdx.x;
+  const int j = t / SP, s = t % SP;       // node slot, lane within the node
+  const int64_t v = (int64_t)blockIdx.x * NB + j;
+  const bool live = v < p.n;
+  // requests that depend on nothing: the node, its list ranges, tile 0
+  const double2 pv = live ? load_pos(p.x, v) : make_double2(0.0, 0.0);
+  const double vx = pv.x, vy = pv.y;
+  int64_t k0 = 0, k1 = 0, f0 = 0, f1 = 0;
+  if (live) {
+    csr_range(p.adj_start, v, p.n_adj, &k0, &k1);
+    csr_range(p.fan_start, v, p.n_fan, &f0, &f1);
+  }
+  double2 st[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int64_t u = t + (int64_t)i * kLanes;
+    st[i] = u < p.n ? load_pos(p.x, u) : make_double2(0.0, 0.0);
+  }
+  // each lane's first spring and triangle (their latency overlaps the
+  // repulsion below)
+  bool has_u = false, has_ab = false;
+  double2 pu = make_double2(0.0, 0.0), pa = pu, pb = pu;
+  if (k0 + s < k1) {
+    const int32_t u = p.adj[k0 + s];
+    if (u >= 0 && u < p.n) {
+      has_u = true;
+      pu = load_pos(p.x, u);
+    }
+  }
+  if (f0 + s < f1) {
+    const int32_t a = p.fan[2 * (f0 + s)], b = p.fan[2 * (f0 + s) + 1];
+    if (a >= 0 && a < p.n && b >= 0 && b < p.n) {
+      has_ab = true;
+      pa = load_pos(p.x, a);
+      pb = load_pos(p.x, b);
+    }
+  }
+  // repulsion (Eq. 1) from the sources base + e, e = s, s + SP, ...; the
+  // node itself adds exactly zero, so it needs no test
+  double fx = 0.0, fy = 0.0;
+  for (int64_t base = 0; base < p.n; base += TILE) {
+    __syncthreads();                       // the previous round is done with src
+#pragma unroll
+    for (int i = 0; i < PER; ++i) src[t + i * kLanes] = st[i];
+    __syncthreads();
+    const int64_t next = base + TILE;
+    if (next < p.n) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int64_t u = next + t + (int64_t)i * kLanes;
+        st[i] = u < p.n ? load_pos(p.x, u) : make_double2(0.0, 0.0);
+      }
+    }
+    const int cnt = (int)((p.n - base) < TILE ? (p.n - base) : TILE);
+#pragma unroll 4
+    for (int e = s; e < cnt; e += SP) {
+      const double2 q2 = src[e];
+      const double ax = vx - q2.x, ay = vy - q2.y;
+      const double q = repulsion_factor(ax * ax + ay * ay, p.C, p.eta);
+      fx += q * ax;
+      fy += q * ay;
+    }
+  }
+  // springs (Eq. 2) and node-edge repulsion (Eq. 3)
+  if (has_u) add_spring(vx, vy, pu.x, pu.y, p.D, p.eta, fx, fy);
+  for (int64_t k = k0 + s + SP; k < k1; k += SP) {
+    const int32_t u = p.adj[k];
+    if (u < 0 || u >= p.n) continue;
+    const double2 q2 = load_pos(p.x, u);
+    add_spring(vx, vy, q2.x, q2.y, p.D, p.eta, fx, fy);
+  }
+  if (has_ab) add_edge(vx, vy, pa.x, pa.y, pb.x, pb.y, p.C, p.eta, fx, fy);
+  for (int64_t k = f0 + s + SP; k < f1; k += SP) {
+    const int32_t a = p.fan[2 * k], b = p.fan[2 * k + 1];
+    if (a < 0 || a >= p.n || b < 0 || b >= p.n) continue;
+    const double2 qa = load_pos(p.x, a), qb = load_pos(p.x, b);
+    add_edge(vx, vy, qa.x, qa.y, qb.x, qb.y, p.C, p.eta, fx, fy);
+  }
+  fx = group_sum<SP>(fx);
+  fy = group_sum<SP>(fy);
   // temperature
   const double fl = sqrt(fx * fx + fy * fy);
   if (fl > p.t) {
     fx *= p.t / fl;
     fy *= p.t / fl;
   }
-  // limiting lines: corner i's line is halfway between the edge opposite
-  // corner i and the corner; from v it is half of -(v's offset) for i = 0,
-  // half of the corner's offset from the edge through v for i = 1, 2
+  // limiting lines of the node's triangles, shared over its lanes
   double scale = 1.0;
-  for (int64_t k = k0; k < k1; ++k) {
+  if (has_ab) scale = triangle_scale(vx, vy, pa.x, pa.y, pb.x, pb.y, fx, fy, p.eta);
+  for (int64_t k = f0 + s + SP; k < f1; k += SP) {
     const int32_t a = p.fan[2 * k], b = p.fan[2 * k + 1];
     if (a < 0 || a >= p.n || b < 0 || b >= p.n) continue;
-    const double P[3][2] = {{vx, vy}, {p.x[2 * a], p.x[2 * a + 1]}, {p.x[2 * b], p.x[2 * b + 1]}};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double* c = P[i];
-      const double* e0 = P[(i + 1) % 3];
-      const double* e1 = P[(i + 2) % 3];
-      const double ex = e1[0] - e0[0], ey = e1[1] - e0[1];
-      const double e2 = ex * ex + ey * ey;
-      if (!(e2 > 0.0)) continue;
-      const double tt = ((c[0] - e0[0]) * ex + (c[1] - e0[1]) * ey) / e2;
-      const double ox = c[0] - (e0[0] + tt * ex), oy = c[1] - (e0[1] + tt * ey);
-      const double rx = i == 0 ? -0.5 * ox : 0.5 * ox, ry = i == 0 ? -0.5 * oy : 0.5 * oy;
-      const double rl = sqrt(rx * rx + ry * ry);
-      if (!(rl > 0.0)) {
-        scale = 0.0;
-        continue;
-      }
-      const double proj = (fx * rx + fy * ry) / rl;
-      if (proj > 0.0) {
-        const double room = rl - p.eta > 0.0 ? rl - p.eta : 0.0;
-        if (proj * scale > room) scale = room / proj;
-      }
-    }
+    const double2 qa = load_pos(p.x, a), qb = load_pos(p.x, b);
+    const double g = triangle_scale(vx, vy, qa.x, qa.y, qb.x, qb.y, fx, fy, p.eta);
+    scale = g < scale ? g : scale;
   }
-  p.y[2 * v] = vx + fx * scale;
-  p.y[2 * v + 1] = vy + fy * scale;
+  scale = group_min<SP>(scale);
+  if (s == 0 && live) {
+    p.y[2 * v] = vx + fx * scale;
+    p.y[2 * v + 1] = vy + fy * scale;
+  }
 }
 
 __global__ __launch_bounds__(256) void widen_kernel(const float* in, double* out, int64_t m) {
@@ -188,12 +314,20 @@ hipError_t launch_layout(const LayoutArgs& a, hipStream_t s) {
   double* cur = a.buf0;
   double* nxt = a.buf1;
   double t = a.t0;
-  const unsigned blocks = (unsigned)((a.n + kNodes - 1) / kNodes);
+  // nodes per workgroup: few (more lanes per node) while the node count
+  // alone would leave compute units idle, more once sources dominate
+  const int nb = a.n < 16384 ? 4 : (a.n < 262144 ? 16 : 64);
+  const unsigned blocks = (unsigned)((a.n + nb - 1) / nb);
   for (int it = 0; it < a.iterations; ++it) {
     p.x = cur;
     p.y = nxt;
     p.t = t;
-    hipLaunchKernelGGL(layout_step_kernel, dim3(blocks), dim3(kNodes * kWaves), 0, s, p);
+    if (nb == 4)
+      hipLaunchKernelGGL((layout_step_kernel<4, 2048>), dim3(blocks), dim3(kLanes), 0, s, p);
+    else if (nb == 16)
+      hipLaunchKernelGGL((layout_step_kernel<16, 1024>), dim3(blocks), dim3(kLanes), 0, s, p);
+    else
+      hipLaunchKernelGGL((layout_step_kernel<64, 1024>), dim3(blocks), dim3(kLanes), 0, s, p);
     double* tmp = cur;
     cur = nxt;
     nxt = tmp;
