@@ -63,6 +63,7 @@ constexpr int KT = MLS_F64_KT; // points per LDS chunk
 // conflicts (a stride of 68 doubles puts rows i and i + 8 on the same
 // banks).
 constexpr int KS = KT + MLS_F64_PAD;
+static_assert(KS % 2 == 0 && KT % 16 == 0, "rows must start on 16-byte boundaries");
 // Waves that run the epilogue at the same time: the epilogue needs a
 // [nodes][features] float64 staging area per wave, and sharing it keeps the
 // kernel's LDS small enough for two workgroups per CU.
@@ -132,6 +133,15 @@ __device__ __forceinline__ double invpow_weight(double ox, double oy, double alp
   return ldexp((double)exp2f((float)(e - ip)), (int)ip);
 }
 
+__device__ __forceinline__ void read4(const double* src, double* dst) {
+  const double2* v = reinterpret_cast<const double2*>(src);
+  const double2 lo = v[0], hi = v[1];
+  dst[0] = lo.x;
+  dst[1] = lo.y;
+  dst[2] = hi.x;
+  dst[3] = hi.y;
+}
+
 // Epilogue EPI: 0 fields, 1 fields and the slopes of the local fits (the
 // extra solves raise the epilogue's register count, so they are separate
 // instantiations and the plain kernels keep two workgroups per CU), 2 the
@@ -194,94 +204,115 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
   const double sx = p.dx * p.inv_h, sy = p.dy * p.inv_h;
   const double qx = exp(-2.0 * sx * sx), qy = exp(-2.0 * sy * sy);
 
-  for (int64_t k0 = 0; k0 < p.n; k0 += KT) {
-    const int kn = (int)((p.n - k0) < KT ? (p.n - k0) : KT);
-    // 1. coordinates in the tile frame
+  // 1. tile-frame coordinates of a chunk, from the prefetched raw data;
+  //    the first chunk's now, each later one right after the MFMA sweep of
+  //    its predecessor (which does not read them)
+  auto put_coords = [&](int kn_) {
     if (tid < KT) {
       double x = 0.0, y = 0.0;
-      if (tid < kn) {
+      if (tid < kn_) {
         x = ((double)pf_x - cx) * p.inv_h;
         y = ((double)pf_y - cy) * p.inv_h;
       }
       ux[tid] = x;
       uy[tid] = y;
     }
-    __syncthreads();
-    if (tid < 2 * KT) {
+  };
+  put_coords((int)(p.n < KT ? p.n : KT));
+  __syncthreads();
+  // (point, attribute) of this thread's first feature element and the step
+  // to its next one (kThreads elements on)
+  const int fk0 = tid / D, fd0 = tid - fk0 * D;
+  const int fks = kThreads / D, fds = kThreads - fks * D;
+
+  for (int64_t k0 = 0; k0 < p.n; k0 += KT) {
+    const int kn = (int)((p.n - k0) < KT ? (p.n - k0) : KT);
+    for (int e = tid; e < 4 * KT; e += kThreads) {
       // 2a. separable Gaussian factors g_c = exp(-(u - e_c)^2), e_c = (c - c_mid) s,
-      //     for one point and one axis.  Start at the node nearest to u (the
-      //     largest factor) and step outwards: g_{c+1} / g_c = exp(2 s (u - e_c) - s^2),
-      //     and that ratio itself shrinks by exp(-2 s^2) per step, so every
-      //     exponent is <= 0 and three exponentials serve the whole row.
-      //     Points past n get weight 0.
-      const int k = tid & (KT - 1);
-      const bool xaxis = tid < KT;
+      //     for one point, one axis and one direction.  Start at the node
+      //     nearest to u (the largest factor) and step outwards:
+      //     g_{c+1} / g_c = exp(2 s (u - e_c) - s^2), and that ratio itself
+      //     shrinks by exp(-2 s^2) per step, so every exponent is <= 0; one
+      //     thread steps up from the nearest node and another down.  Points
+      //     past n get weight 0.
+      const int k = e & (KT - 1);
+      const bool xaxis = (e & KT) == 0;
+      const bool up = e < 2 * KT;
       const int cnt = xaxis ? kCols : L::kRows;
       const int mid = cnt / 2;
       const double s = xaxis ? sx : sy;
       const double q = xaxis ? qx : qy;
       double* g = xaxis ? gx : gy;
+      // each direction owns half of the row when there is no stepping
+      const int h0 = up ? 0 : mid, h1 = up ? mid : cnt;
       if (INV) {
         // inverse-distance weights do not separate: the tables hold the
         // node offsets, and the A operand forms the weight per pair
         const double u = k < kn ? (xaxis ? ux[k] : uy[k]) : 0.0;
-        for (int c = 0; c < cnt; ++c)
+        for (int c = h0; c < h1; ++c)
           g[c * KS + k] = k < kn ? u - (double)(c - mid) * s : __builtin_inf();
       } else if (k < kn) {
         const double u = xaxis ? ux[k] : uy[k];
         const double t = u / s + (double)mid;
-        int cs = (int)fmin(fmax(rint(t), 0.0), (double)(cnt - 1));
+        const int cs = (int)fmin(fmax(rint(t), 0.0), (double)(cnt - 1));
         const double dc = u - (double)(cs - mid) * s;
-        double gv = exp(-(dc * dc));
-        g[cs * KS + k] = gv;
-        double r = exp(2.0 * s * dc - s * s);
+        const double gv = exp(-(dc * dc));
+        double r = exp((up ? 2.0 : -2.0) * s * dc - s * s);
         double v = gv;
-        for (int c = cs + 1; c < cnt; ++c) {
-          v *= r;
-          r *= q;
-          g[c * KS + k] = v;
-        }
-        r = exp(-2.0 * s * dc - s * s);
-        v = gv;
-        for (int c = cs - 1; c >= 0; --c) {
-          v *= r;
-          r *= q;
-          g[c * KS + k] = v;
+        if (up) {
+          g[cs * KS + k] = gv;
+          for (int c = cs + 1; c < cnt; ++c) {
+            v *= r;
+            r *= q;
+            g[c * KS + k] = v;
+          }
+        } else {
+          for (int c = cs - 1; c >= 0; --c) {
+            v *= r;
+            r *= q;
+            g[c * KS + k] = v;
+          }
         }
       } else {
-        for (int c = 0; c < cnt; ++c) g[c * KS + k] = 0.0;
-      }
-    } else {
-      // 2b. moment monomials of the tile-frame coordinates
-      for (int e = tid - 2 * KT; e < nmom * KT; e += kThreads - 2 * KT) {
-        const int k = e % KT, j = e / KT;
-        // exponents of monomial j (ordered by total degree, then by y power)
-        int t = 0;
-        while ((t + 1) * (t + 2) / 2 <= j) ++t;
-        const int b = j - t * (t + 1) / 2, a = t - b;
-        double v = 1.0;
-        for (int q = 0; q < a; ++q) v *= ux[k];
-        for (int q = 0; q < b; ++q) v *= uy[k];
-        G[j * KS + k] = v;
+        for (int c = h0; c < h1; ++c) g[c * KS + k] = 0.0;
       }
     }
+    // 2b. moment monomials of the tile-frame coordinates
+    for (int e = tid; e < nmom * KT; e += kThreads) {
+      const int k = e % KT, j = e / KT;
+      // exponents of monomial j (ordered by total degree, then by y power)
+      int t = 0;
+      while ((t + 1) * (t + 2) / 2 <= j) ++t;
+      const int b = j - t * (t + 1) / 2, a = t - b;
+      double v = 1.0;
+      for (int q = 0; q < a; ++q) v *= ux[k];
+      for (int q = 0; q < b; ++q) v *= uy[k];
+      G[j * KS + k] = v;
+    }
     // 2c. basis x attribute products from the prefetched values
+    {
+      int k = fk0, d = fd0;
 #pragma unroll
-    for (int it = 0; it < L::kValRegs; ++it) {
-      const int e = tid + it * kThreads;
-      if (e < KT * D) {
-        const int k = e / D, d = e - k * D;
-        const double f = (double)pf_v[it];
-        G[(nmom + d) * KS + k] = f;
-        if (m >= 3) {
-          const double bx = ux[k], by = uy[k];
-          G[(nmom + D + d) * KS + k] = bx * f;
-          G[(nmom + 2 * D + d) * KS + k] = by * f;
-          if (m >= 6) {
-            G[(nmom + 3 * D + d) * KS + k] = bx * bx * f;
-            G[(nmom + 4 * D + d) * KS + k] = bx * by * f;
-            G[(nmom + 5 * D + d) * KS + k] = by * by * f;
+      for (int it = 0; it < L::kValRegs; ++it) {
+        if (k < KT) {
+          const double f = (double)pf_v[it];
+          G[(nmom + d) * KS + k] = f;
+          if (m >= 3) {
+            const double bx = ux[k], by = uy[k];
+            G[(nmom + D + d) * KS + k] = bx * f;
+            G[(nmom + 2 * D + d) * KS + k] = by * f;
+            if (m >= 6) {
+              G[(nmom + 3 * D + d) * KS + k] = bx * bx * f;
+              G[(nmom + 4 * D + d) * KS + k] = bx * by * f;
+              G[(nmom + 5 * D + d) * KS + k] = by * by * f;
+            }
           }
+        }
+        k += fks;
+        d += fds;
+        if (d >= D) {
+          d -= D;
+          ++k;
         }
       }
     }
@@ -295,20 +326,14 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     if (MLS_F64_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll MLS_F64_KG_UNROLL
     for (int kg = 0; kg < KT; kg += 16) {
-      const double* gxr = gx + i * KS + kg + kq;
-      double ax[4] = {gxr[0], gxr[1], gxr[2], gxr[3]};
-      double ay[R][4];
+      // four consecutive doubles of a row as two 16-byte reads (rows start
+      // on 16-byte boundaries: KS is even and kg + kq a multiple of 4)
+      double ax[4], ay[R][4], bv[NT][4];
+      read4(gx + i * KS + kg + kq, ax);
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        const double* gyr = gy + (wave * R + t) * KS + kg + kq;
-        ay[t][0] = gyr[0]; ay[t][1] = gyr[1]; ay[t][2] = gyr[2]; ay[t][3] = gyr[3];
-      }
-      double bv[NT][4];
+      for (int t = 0; t < R; ++t) read4(gy + (wave * R + t) * KS + kg + kq, ay[t]);
 #pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        const double* gr = G + (q * 16 + i) * KS + kg + kq;
-        bv[q][0] = gr[0]; bv[q][1] = gr[1]; bv[q][2] = gr[2]; bv[q][3] = gr[3];
-      }
+      for (int q = 0; q < NT; ++q) read4(G + (q * 16 + i) * KS + kg + kq, bv[q]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
@@ -321,6 +346,7 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
       }
     }
     if (MLS_F64_SETPRIO) __builtin_amdgcn_s_setprio(0);
+    if (k0 + KT < p.n) put_coords((int)((p.n - k0 - KT) < KT ? (p.n - k0 - KT) : KT));
     __syncthreads();
   }
 
