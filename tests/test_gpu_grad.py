@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
-GRAD_LP = 5e-3
+GRAD_LP = 1e-3
 
 
 def note(msg):
