@@ -591,6 +591,38 @@ int oracle_layout(const double* pos_in, int64_t n, const int32_t* adj_start,
   return 0;
 }
 
+/*
+ * One layout iteration at temperature t for the listed nodes only:
+ * pos_out[2 i], pos_out[2 i + 1] is node nodes[i] after the iteration, from
+ * the positions pos_in[n][2] (the same move as oracle_layout's first
+ * iteration, so large meshes can be checked on a sample of nodes).
+ * Returns 0, or -1 on invalid arguments.
+ */
+int oracle_layout_step_nodes(const double* pos_in, int64_t n, const int32_t* adj_start,
+                             const int32_t* adj, const int32_t* fan_start, const int32_t* fan,
+                             double C, double D, double eta, double t, const int64_t* nodes,
+                             int64_t m, int32_t nthreads, double* pos_out) {
+  if (!pos_in || !pos_out || n < 1 || !adj_start || !fan_start || !nodes || m < 0 ||
+      !(D > 0.0) || !(eta > 0.0) || !(t >= 0.0))
+    return -1;
+  for (int64_t i = 0; i < m; ++i)
+    if (nodes[i] < 0 || nodes[i] >= n) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t v = nodes[i];
+    double mv[2];
+    layout_move(pos_in, n, v, adj_start, adj, fan_start, fan, C, D, eta, t, mv);
+    pos_out[2 * i] = pos_in[2 * v] + mv[0];
+    pos_out[2 * i + 1] = pos_in[2 * v + 1] + mv[1];
+  }
+  return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Marching squares                                                        */
 /* ---------------------------------------------------------------------- */

@@ -69,6 +69,9 @@ def _load():
     lib.oracle_rigid_grid.restype = ctypes.c_int
     lib.oracle_layout.argtypes = [P, i64, P, P, P, P, f64, f64, f64, f64, f64, i32, i32, P]
     lib.oracle_layout.restype = ctypes.c_int
+    lib.oracle_layout_step_nodes.argtypes = [P, i64, P, P, P, P, f64, f64, f64, f64, P, i64,
+                                             i32, P]
+    lib.oracle_layout_step_nodes.restype = ctypes.c_int
     for name in ("oracle_contour_f64", "oracle_contour_f32"):
         fn = getattr(lib, name)
         fn.argtypes = [P, i32, i32, f64, f64, f64, f64, P, i32, i32, P, P, P, i64]
@@ -196,6 +199,24 @@ def layout(pos, mesh, C, D, eta, t0, lam, iterations, threads=0):
                                _ptr(out))
     if rc != 0:
         raise ValueError("oracle_layout rejected its arguments")
+    return out
+
+
+def layout_step_nodes(pos, mesh, C, D, eta, t, nodes, threads=0):
+    """One layout iteration at temperature t (Sec. 3.2) for the listed nodes
+    only: their positions (m, 2) after it, float64; the move is the one
+    `layout` makes in its first iteration."""
+    x = np.ascontiguousarray(pos, dtype=np.float64)
+    n = x.shape[0]
+    arrs = [np.ascontiguousarray(mesh[k], dtype=np.int32)
+            for k in ("adj_start", "adj", "fan_start", "fan")]
+    idx = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.empty((idx.size, 2), dtype=np.float64)
+    rc = _load().oracle_layout_step_nodes(_ptr(x), n, *[_ptr(a) for a in arrs], float(C),
+                                          float(D), float(eta), float(t), _ptr(idx), idx.size,
+                                          int(threads), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_layout_step_nodes rejected its arguments")
     return out
 
 

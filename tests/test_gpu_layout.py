@@ -93,3 +93,52 @@ def test_layout_ignores_malformed_lists(torch_dev):
                C=1e-3, D=0.1, eta=1e-4, t0=0.01, lam=0.9, iterations=3)
     torch.cuda.synchronize()
     assert torch.isfinite(pts).all()
+
+
+def test_layout_bench_shape(torch_dev, oracle):
+    """The 2245-node timing-table mesh with the bench's parameters: parity
+    after 10 iterations, and no flipped triangle after the bench's 1000."""
+    from paper_1408_0677_amd import api, workloads as wl
+    note("case layout 2245 nodes, bench parameters")
+    pts, mesh, prm = wl.layout_workload(2245)
+    p32 = pts.astype(np.float32)
+    M = to_dev(torch_dev, mesh)
+    P = torch_dev.from_numpy(p32.copy()).cuda()
+    api.layout(P, M, iterations=10, **prm)
+    torch_dev.cuda.synchronize()
+    ref = oracle.layout(p32.astype(np.float64), mesh, iterations=10, **prm)
+    err = np.abs(P.cpu().numpy().astype(np.float64) - ref).max() / 600.0
+    note(f"10 iterations: max position error {err:.3e} of the canvas")
+    assert err <= 2e-6
+    P = torch_dev.from_numpy(p32.copy()).cuda()
+    api.layout(P, M, iterations=1000, **prm)
+    torch_dev.cuda.synchronize()
+    out = P.cpu().numpy().astype(np.float64)
+    tri = mesh["triangles"]
+    assert np.all(np.isfinite(out))
+    assert np.all(np.sign(signed_areas(p32.astype(np.float64), tri)) ==
+                  np.sign(signed_areas(out, tri)))
+
+
+@pytest.mark.parametrize("n", [65536, 300000])
+def test_layout_large_meshes_sampled(torch_dev, oracle, n):
+    """Meshes large enough for the 16- and 64-node workgroup layouts: one
+    iteration, checked against the oracle on a sample of nodes."""
+    from paper_1408_0677_amd import api, workloads as wl
+    note(f"case layout {n} nodes, sampled")
+    rng = np.random.default_rng(n)
+    p32 = (rng.random((n, 2)) * 600.0).astype(np.float32)
+    mesh = wl.mesh_arrays(p32.astype(np.float64))
+    prm = params_for(p32.astype(np.float64), mesh)
+    P = torch_dev.from_numpy(p32.copy()).cuda()
+    api.layout(P, to_dev(torch_dev, mesh), iterations=1, **prm)
+    torch_dev.cuda.synchronize()
+    got = P.cpu().numpy().astype(np.float64)
+    nodes = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 1000)]))
+    ref = oracle.layout_step_nodes(p32.astype(np.float64), mesh, C=prm["C"], D=prm["D"],
+                                   eta=prm["eta"], t=prm["t0"], nodes=nodes)
+    err = np.abs(got[nodes] - ref).max() / 600.0
+    moved = np.abs(ref - p32[nodes]).max()
+    note(f"max position error {err:.3e} of the canvas over {nodes.size} nodes, moved {moved:.3e}")
+    assert moved > 1e-3
+    assert err <= 2e-6

@@ -133,3 +133,21 @@ def test_single_triangle_closed_form(oracle):
         R = foot - x[v]
         exp[v] += -C * R / (np.dot(R, R) + eta)
     np.testing.assert_allclose(out - x, exp, rtol=1e-11, atol=1e-16)
+
+
+def test_step_nodes_matches_full_iteration(oracle):
+    """The sampled-node entry makes exactly the first iteration's move of
+    the full layout, for any subset and order of nodes."""
+    from paper_1408_0677_amd import workloads as wl
+    rng = np.random.default_rng(41)
+    pts = rng.random((150, 2))
+    mesh = wl.mesh_arrays(pts)
+    src = np.repeat(np.arange(150), np.diff(mesh["adj_start"]))
+    D = float(np.linalg.norm(pts[src] - pts[mesh["adj"]], axis=1).mean())
+    prm = dict(C=D ** 3, D=D, eta=1e-3 * D)
+    full = oracle.layout(pts, mesh, t0=0.3 * D, lam=0.5, iterations=1, **prm)
+    nodes = rng.permutation(150)[:60]
+    part = oracle.layout_step_nodes(pts, mesh, t=0.3 * D, nodes=nodes, **prm)
+    assert np.array_equal(part, full[nodes])
+    with pytest.raises(ValueError):
+        oracle.layout_step_nodes(pts, mesh, t=0.3 * D, nodes=[150], **prm)
