@@ -88,18 +88,20 @@ def test_exact_hits_take_the_mean(torch_dev, oracle):
     assert st["max_err_pass"] <= TOL
 
 
+@pytest.mark.parametrize("basis", ["linear", "constant"])
 @pytest.mark.parametrize("n", [306, 2245])
-def test_table1_shapes_sampled(torch_dev, oracle, n):
-    """The timing-table shape (600 x 600, N uniform, D = 2, linear, alpha = 1)
-    on sampled nodes."""
+def test_table1_shapes_sampled(torch_dev, oracle, n, basis):
+    """The timing-table shape (600 x 600, N uniform, D = 2, alpha = 1) on
+    sampled nodes: Affine MLS (linear basis) and Mean MLS (constant
+    basis), as the bench times them."""
     from paper_1408_0677_amd import workloads as wl
     w = wl.t1(n)
-    note(f"case {w.name}")
-    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis=w.basis, weight=w.weight,
+    note(f"case {w.name} {basis}")
+    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis=basis, weight=w.weight,
                      h=w.h, alpha=w.alpha)
     rng = np.random.default_rng(n)
     pix = rng.choice(600 * 600, 3000, replace=False)
-    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis=w.basis, weight=w.weight,
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis=basis, weight=w.weight,
                                  h=w.h, alpha=w.alpha, pixels=pix)
     st = compare(F.reshape(2, -1)[:, pix], deg.ravel()[pix], of, od, dm, w.values)
     note(str({k: v for k, v in st.items() if k != "per_field_max_pass"}))

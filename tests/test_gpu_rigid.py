@@ -103,3 +103,25 @@ def test_rigid_exact_hits_and_refusals(torch_dev, oracle):
         api.fit_grad(P, torch.rand(20, 2, device="cuda"), grid, basis="rigid")
     assert "UNSUPPORTED" in str(ei.value)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [306, 2245])
+def test_rigid_table1_shapes_sampled(torch_dev, oracle, n):
+    """Rigid MLS at the timing-table shape the bench times (600 x 600, N
+    uniform, inverse-distance weight, alpha = 1), on sampled nodes."""
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.t1(n)
+    note(f"case rigid {w.name}")
+    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, weight=w.weight, h=w.h,
+                     alpha=w.alpha)
+    rng = np.random.default_rng(n + 1)
+    pix = rng.choice(600 * 600, 3000, replace=False)
+    of, od = oracle.rigid_grid(w.points, w.values, w.grid, weight=w.weight, h=w.h,
+                               alpha=w.alpha, pixels=pix)
+    S = np.ptp(w.values.astype(np.float64), axis=0)
+    gd = deg.ravel()[pix]
+    assert np.array_equal(gd, od)
+    ok = od != 255
+    err = (np.abs(F.reshape(2, -1)[:, pix] - of) / S[:, None])[:, ok].max()
+    note(f"max relative error {err:.3e} over {int(ok.sum())} nodes")
+    assert ok.sum() > 2900 and err <= TOL
