@@ -164,16 +164,28 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
   const int cw = p.W - 1;
   w.lo = __builtin_inff();
   w.hi = -__builtin_inff();
+  // row and column of the chunk's first cell: one division per wave; each
+  // lane's cells lie at most kCellsPerWave further on, so a few steps of
+  // one row reach them
+  const int64_t base = chunk * kCellsPerWave;
+  const int64_t row0 = base / cw;
+  const int col0 = (int)(base - row0 * cw);
 #pragma unroll
   for (int q = 0; q < kCellsPerLane; ++q) {
-    const int64_t cell = chunk * kCellsPerWave + q * 64 + lane;
+    const int64_t cell = base + q * 64 + lane;
     w.cell[q] = cell;
     w.in[q] = cell < p.cells;
     w.c[q] = Corners{0.f, 0.f, 0.f, 0.f, false};
     w.i[q] = w.j[q] = 0;
     if (w.in[q]) {
-      w.i[q] = (int)(cell / cw);
-      w.j[q] = (int)(cell % cw);
+      int col = col0 + q * 64 + lane;
+      int row = (int)row0;
+      while (col >= cw) {
+        col -= cw;
+        ++row;
+      }
+      w.i[q] = row;
+      w.j[q] = col;
       w.c[q] = load_corners(f, p.W, w.i[q], w.j[q]);
       if (w.c[q].valid) {
         w.lo = fminf(w.lo, fminf(fminf(w.c[q].v0, w.c[q].v1), fminf(w.c[q].v2, w.c[q].v3)));
