@@ -50,16 +50,6 @@ struct Corners {
   bool valid;
 };
 
-__device__ __forceinline__ Corners load_corners(const float* f, int W, int i, int j) {
-  Corners c;
-  c.v0 = f[(int64_t)i * W + j];
-  c.v1 = f[(int64_t)i * W + j + 1];
-  c.v2 = f[(int64_t)(i + 1) * W + j + 1];
-  c.v3 = f[(int64_t)(i + 1) * W + j];
-  c.valid = !(isnan(c.v0) || isnan(c.v1) || isnan(c.v2) || isnan(c.v3));
-  return c;
-}
-
 __device__ __forceinline__ int cell_case(const Corners& c, float iso) {
   if (!c.valid) return 255;
   return (c.v0 >= iso ? 1 : 0) | (c.v1 >= iso ? 2 : 0) | (c.v2 >= iso ? 4 : 0) |
@@ -170,27 +160,40 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
   const int64_t base = chunk * kCellsPerWave;
   const int64_t row0 = base / cw;
   const int col0 = (int)(base - row0 * cw);
+  int64_t at[kCellsPerLane];    // index of corner 0; cells past the grid read cell 0
 #pragma unroll
   for (int q = 0; q < kCellsPerLane; ++q) {
     const int64_t cell = base + q * 64 + lane;
     w.cell[q] = cell;
     w.in[q] = cell < p.cells;
-    w.c[q] = Corners{0.f, 0.f, 0.f, 0.f, false};
-    w.i[q] = w.j[q] = 0;
-    if (w.in[q]) {
-      int col = col0 + q * 64 + lane;
-      int row = (int)row0;
-      while (col >= cw) {
-        col -= cw;
-        ++row;
-      }
-      w.i[q] = row;
-      w.j[q] = col;
-      w.c[q] = load_corners(f, p.W, w.i[q], w.j[q]);
-      if (w.c[q].valid) {
-        w.lo = fminf(w.lo, fminf(fminf(w.c[q].v0, w.c[q].v1), fminf(w.c[q].v2, w.c[q].v3)));
-        w.hi = fmaxf(w.hi, fmaxf(fmaxf(w.c[q].v0, w.c[q].v1), fmaxf(w.c[q].v2, w.c[q].v3)));
-      }
+    int col = col0 + q * 64 + lane;
+    int row = (int)row0;
+    while (col >= cw) {
+      col -= cw;
+      ++row;
+    }
+    if (!w.in[q]) row = col = 0;
+    w.i[q] = row;
+    w.j[q] = col;
+    at[q] = (int64_t)row * p.W + col;
+  }
+  // every corner load in flight before the first is used
+  float v[kCellsPerLane][4];
+#pragma unroll
+  for (int q = 0; q < kCellsPerLane; ++q) {
+    v[q][0] = f[at[q]];
+    v[q][1] = f[at[q] + 1];
+    v[q][2] = f[at[q] + p.W + 1];
+    v[q][3] = f[at[q] + p.W];
+  }
+#pragma unroll
+  for (int q = 0; q < kCellsPerLane; ++q) {
+    Corners c{v[q][0], v[q][1], v[q][2], v[q][3], false};
+    c.valid = w.in[q] && !(isnan(c.v0) || isnan(c.v1) || isnan(c.v2) || isnan(c.v3));
+    w.c[q] = c;
+    if (c.valid) {
+      w.lo = fminf(w.lo, fminf(fminf(c.v0, c.v1), fminf(c.v2, c.v3)));
+      w.hi = fmaxf(w.hi, fmaxf(fmaxf(c.v0, c.v1), fmaxf(c.v2, c.v3)));
     }
   }
 }
