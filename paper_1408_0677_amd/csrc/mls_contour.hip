@@ -81,10 +81,6 @@ __device__ __forceinline__ int case_segments(int cs, const Corners& c, float iso
   return 1;
 }
 
-__device__ __forceinline__ int segment_count(int cs) {
-  return (cs == 5 || cs == 10) ? 2 : ((cs == 0 || cs == 15 || cs == 255) ? 0 : 1);
-}
-
 struct GridD {
   double x0, y0, dx, dy;
 };
@@ -143,6 +139,9 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
 // lane's valid corners (an isovalue outside it crosses none of them).
 struct WaveCells {
   Corners c[kCellsPerLane];
+  // corner range of each cell (+inf, -inf when the cell is outside the grid
+  // or has a NaN corner): the cell has segments iff clo < iso <= chi
+  float clo[kCellsPerLane], chi[kCellsPerLane];
   int i[kCellsPerLane], j[kCellsPerLane];
   int64_t cell[kCellsPerLane];
   bool in[kCellsPerLane];
@@ -191,10 +190,10 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
     Corners c{v[q][0], v[q][1], v[q][2], v[q][3], false};
     c.valid = w.in[q] && !(isnan(c.v0) || isnan(c.v1) || isnan(c.v2) || isnan(c.v3));
     w.c[q] = c;
-    if (c.valid) {
-      w.lo = fminf(w.lo, fminf(fminf(c.v0, c.v1), fminf(c.v2, c.v3)));
-      w.hi = fmaxf(w.hi, fmaxf(fmaxf(c.v0, c.v1), fmaxf(c.v2, c.v3)));
-    }
+    w.clo[q] = c.valid ? fminf(fminf(c.v0, c.v1), fminf(c.v2, c.v3)) : __builtin_inff();
+    w.chi[q] = c.valid ? fmaxf(fmaxf(c.v0, c.v1), fmaxf(c.v2, c.v3)) : -__builtin_inff();
+    w.lo = fminf(w.lo, w.clo[q]);
+    w.hi = fmaxf(w.hi, w.chi[q]);
   }
 }
 
@@ -222,12 +221,19 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(Cont
           p.cases[((int64_t)d * p.n_iso + k) * p.cells + w.cell[q]] =
               (uint8_t)cell_case(w.c[q], iso);
     }
-    // a cell has segments iff min < iso <= max over its corners
+    // a cell has segments iff min < iso <= max over its corners; it has two
+    // iff it is a saddle (case 5 or 10: diagonal corners on one side, the
+    // other diagonal on the other), found on whole-wave masks
     if (__any(iso > w.lo && iso <= w.hi)) {
 #pragma unroll
       for (int q = 0; q < kCellsPerLane; ++q) {
-        const int ns = w.in[q] ? segment_count(cell_case(w.c[q], iso)) : 0;
-        count += __popcll(__ballot(ns >= 1)) + __popcll(__ballot(ns == 2));
+        const uint64_t ok = __ballot(w.clo[q] < iso && iso <= w.chi[q]);
+        if (ok == 0) continue;
+        const Corners& c = w.c[q];
+        const uint64_t a0 = __ballot(c.v0 >= iso), a1 = __ballot(c.v1 >= iso);
+        const uint64_t a2 = __ballot(c.v2 >= iso), a3 = __ballot(c.v3 >= iso);
+        const uint64_t saddle = ok & ~(a0 ^ a2) & ~(a1 ^ a3) & (a0 ^ a1);
+        count += __popcll(ok) + __popcll(saddle);
       }
     }
     if (lane == 0) p.counts[((int64_t)d * p.n_iso + k) * p.nchunk + chunk] = (int32_t)count;
@@ -328,7 +334,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(Conto
     int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
 #pragma unroll
     for (int q = 0; q < kCellsPerLane; ++q) {
+      // no lane's cell q crosses iso: nothing to place or write (the range is
+      // formed here rather than kept per cell, which would cost registers)
       const Corners cq = w.c[q];
+      if (__ballot(cq.valid && fminf(fminf(cq.v0, cq.v1), fminf(cq.v2, cq.v3)) < iso &&
+                   iso <= fmaxf(fmaxf(cq.v0, cq.v1), fmaxf(cq.v2, cq.v3))) == 0)
+        continue;
       const int iq = w.i[q], jq = w.j[q];
       const int cs = w.in[q] ? cell_case(cq, iso) : 255;
       int a0, a1, b0, b1;
