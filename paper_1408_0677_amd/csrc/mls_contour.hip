@@ -334,19 +334,24 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(Conto
     int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
 #pragma unroll
     for (int q = 0; q < kCellsPerLane; ++q) {
-      // no lane's cell q crosses iso: nothing to place or write (the range is
-      // formed here rather than kept per cell, which would cost registers)
+      // cells of this slot with one segment or more, and the saddles among
+      // them (two segments), as whole-wave masks, as in the count pass; the
+      // range is formed here rather than kept per cell, which would cost
+      // registers.  A slot no lane's cell crosses has nothing to write.
       const Corners cq = w.c[q];
-      if (__ballot(cq.valid && fminf(fminf(cq.v0, cq.v1), fminf(cq.v2, cq.v3)) < iso &&
-                   iso <= fmaxf(fmaxf(cq.v0, cq.v1), fmaxf(cq.v2, cq.v3))) == 0)
-        continue;
-      const int iq = w.i[q], jq = w.j[q];
-      const int cs = w.in[q] ? cell_case(cq, iso) : 255;
-      int a0, a1, b0, b1;
-      const int ns = w.in[q] ? case_segments(cs, cq, iso, a0, a1, b0, b1) : 0;
-      const uint64_t one = __ballot(ns >= 1), two = __ballot(ns == 2);
+      const bool has = cq.valid && fminf(fminf(cq.v0, cq.v1), fminf(cq.v2, cq.v3)) < iso &&
+                       iso <= fmaxf(fmaxf(cq.v0, cq.v1), fmaxf(cq.v2, cq.v3));
+      const uint64_t one = __ballot(has);
+      if (one == 0) continue;
+      const uint64_t m0 = __ballot(cq.v0 >= iso), m1 = __ballot(cq.v1 >= iso);
+      const uint64_t m2 = __ballot(cq.v2 >= iso), m3 = __ballot(cq.v3 >= iso);
+      const uint64_t two = one & ~(m0 ^ m2) & ~(m1 ^ m3) & (m0 ^ m1);
       const int64_t base = run + __popcll(one & below) + __popcll(two & below);
       run += __popcll(one) + __popcll(two);
+      if (!has) continue;
+      const int iq = w.i[q], jq = w.j[q];
+      int a0, a1, b0, b1;
+      const int ns = case_segments(cell_case(cq, iso), cq, iso, a0, a1, b0, b1);
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2) {
         const int64_t o = base + s2;
