@@ -155,8 +155,18 @@ def layout(pos, mesh: dict, C: float, D: float, eta: float, t0: float, lam: floa
     device tensor, updated in place and returned; ``mesh`` holds int32 device
     tensors adj_start (n+1), adj, fan_start (n+1), fan (T, 2) or flat."""
     import torch
-    assert pos.dtype == torch.float32 and pos.is_contiguous()
+    if not (isinstance(pos, torch.Tensor) and pos.is_cuda and pos.dtype == torch.float32
+            and pos.is_contiguous() and pos.dim() == 2 and pos.shape[1] == 2):
+        raise ValueError("pos must be a contiguous float32 (n, 2) device tensor")
     n = pos.shape[0]
+    for key in ("adj_start", "adj", "fan_start", "fan"):
+        t = mesh[key]
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32
+                and t.is_contiguous() and t.device == pos.device):
+            raise ValueError(f"mesh['{key}'] must be a contiguous int32 tensor on {pos.device}")
+    for key in ("adj_start", "fan_start"):
+        if mesh[key].numel() != n + 1:
+            raise ValueError(f"mesh['{key}'] must hold n + 1 = {n + 1} entries")
     adj, fan = mesh["adj"], mesh["fan"]
     n_adj = int(adj.numel())
     n_fan = int(fan.numel()) // 2

@@ -182,3 +182,18 @@ def _layout(lib, n=10, n_adj=4, n_fan=2, prm=(1.0, 0.1, 1e-4, 0.01, 0.99), iters
 def test_layout_arguments_rejected_before_device(lib, kwargs, needle):
     assert _layout(lib, **kwargs) == -1
     assert needle in lib.mls_last_error(), lib.mls_last_error()
+
+
+def test_layout_binding_rejects_host_and_mistyped_arrays():
+    """The binding refuses host tensors and mesh arrays of the wrong type or
+    length before anything reaches the library."""
+    import torch
+    from paper_1408_0677_amd import api
+    mesh = {"adj_start": torch.zeros(4, dtype=torch.int32), "adj": torch.zeros(0, dtype=torch.int32),
+            "fan_start": torch.zeros(4, dtype=torch.int32), "fan": torch.zeros(0, dtype=torch.int32)}
+    with pytest.raises(ValueError, match="device tensor"):
+        api.layout(torch.zeros(3, 2), mesh, C=1.0, D=1.0, eta=1e-3, t0=0.1, lam=0.9,
+                   iterations=1)
+    with pytest.raises(ValueError, match="device tensor"):
+        api.layout(torch.zeros(3, 2, dtype=torch.float64), mesh, C=1.0, D=1.0, eta=1e-3,
+                   t0=0.1, lam=0.9, iterations=1)

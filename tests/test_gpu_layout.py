@@ -142,3 +142,28 @@ def test_layout_large_meshes_sampled(torch_dev, oracle, n):
     note(f"max position error {err:.3e} of the canvas over {nodes.size} nodes, moved {moved:.3e}")
     assert moved > 1e-3
     assert err <= 2e-6
+
+
+def test_layout_binding_checks_mesh_arrays(torch_dev):
+    """Mesh arrays of the wrong type, place or length are refused by the
+    binding instead of being read as something else."""
+    import torch
+    from paper_1408_0677_amd import api, workloads as wl
+    note("case layout binding checks")
+    rng = np.random.default_rng(2)
+    pts = rng.random((40, 2)).astype(np.float32)
+    mesh = to_dev(torch, wl.mesh_arrays(pts))
+    P = torch.from_numpy(pts).cuda()
+    prm = dict(C=1e-3, D=0.1, eta=1e-4, t0=0.01, lam=0.9, iterations=1)
+    bad = dict(mesh, adj=mesh["adj"].long())
+    with pytest.raises(ValueError, match="int32"):
+        api.layout(P, bad, **prm)
+    bad = dict(mesh, fan=mesh["fan"].cpu())
+    with pytest.raises(ValueError, match="int32"):
+        api.layout(P, bad, **prm)
+    bad = dict(mesh, adj_start=mesh["adj_start"][:-1].contiguous())
+    with pytest.raises(ValueError, match="n \\+ 1"):
+        api.layout(P, bad, **prm)
+    api.layout(P, mesh, **prm)
+    torch.cuda.synchronize()
+    assert torch.isfinite(P).all()
