@@ -315,7 +315,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
-              "shards by node rows, which this build does not run across GPUs.",
+              "shards by node rows, which this library does not yet run across GPUs.",
               file=sys.stderr)
         sys.exit(2)
 

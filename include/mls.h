@@ -52,7 +52,7 @@ typedef enum {
   MLS_ERR_CAPACITY = -3,      /* output buffer too small (contour) */
   MLS_ERR_DEVICE = -4,        /* HIP runtime error, wrong device */
   MLS_ERR_OVER_BUDGET = -5,   /* (server) request or point set exceeds the budget */
-  MLS_ERR_UNSUPPORTED = -7,   /* valid request this build does not run */
+  MLS_ERR_UNSUPPORTED = -7,   /* valid request the library does not run */
   MLS_PENDING = 1             /* (server) request not finished yet */
 } mls_status;
 
@@ -175,7 +175,7 @@ void mls_context_destroy(mls_context* ctx);
  *  d_fields  float32 [d][height][width] output, device
  *  d_degree  uint8 [height][width] output (accepted degree, 255 for
  *            undetermined), device, or NULL
- * Supported in this build: the Gaussian weight with all three bases and all
+ * Supported: the Gaussian weight with all three bases and all
  * precisions; the Wendland C2 weight with the 16-bit precisions (through a
  * device cell list); the inverse-distance weight with MLS_PREC_F64 on grids
  * with nonzero dx and dy (a node that coincides exactly with data points
