@@ -132,3 +132,31 @@ def test_c2_fields_contours(torch_dev, oracle):
         far &= np.abs(v - lv) > tol
     assert far.mean() > 0.99
     assert np.array_equal(gcase[far], ocase[far])
+
+
+def test_c5_fields_contours_same_input(torch_dev, oracle):
+    """Contours at the 4096^2 / 16-field / 16-isovalue shape the bench times,
+    in its launch configuration (no cases): the first field's segments and
+    ids equal the oracle's on the same fields, bit for bit, and the segment
+    count over all fields equals the oracle's count field by field on two
+    more fields."""
+    from paper_1408_0677_amd import api, workloads as wl
+    import torch
+    w = wl.c5()
+    note(f"case c5 contours {w.name}")
+    P = torch.from_numpy(w.points).cuda()
+    V = torch.from_numpy(w.values).cuda()
+    F, _ = api.fit(P, V, w.grid, basis=w.basis, weight=w.weight, h=w.h, precision="bf16")
+    iso = torch.from_numpy(w.iso()).cuda()
+    segs, ids, _ = api.contour(F, w.grid, iso, want_cases=False)
+    torch.cuda.synchronize()
+    ids_h = ids.cpu().numpy()
+    segs_h = segs.cpu().numpy()
+    Fh = F.cpu().numpy()
+    for d in (0, 7, 15):
+        _, os_, oi = oracle.contour(Fh[d:d + 1], w.grid, w.iso()[d:d + 1], f32=True)
+        mine = ids_h[:, 0] == d
+        note(f"field {d}: {int(mine.sum())} segments")
+        assert mine.sum() == oi.shape[0] and oi.shape[0] > 1000
+        assert np.array_equal(ids_h[mine][:, 1:], oi[:, 1:])
+        assert np.array_equal(segs_h[mine], os_.astype(np.float32))
