@@ -131,27 +131,20 @@ __device__ __forceinline__ double triangle_scale(double vx, double vy, double ax
 // C / (|V|^3 + eta) for |V|^2 = r2, the factor of V in the repulsion of
 // Eq. 1.  |V| comes from the hardware reciprocal square root and the
 // quotient from the hardware reciprocal (each an estimate good to about 23
-// bits), refined by two Newton steps and a final residual step: within a
-// few ulp of the correctly rounded value, in about half the instructions of
-// the IEEE square root and division, and without a branch.  V = 0 (the node
-// itself, or a coincident node) takes |V| = 1 so that the factor stays
-// finite and its product with V is exactly zero.
+// bits), refined by one Newton step each (about 46 bits) and a final
+// residual step on the quotient: within about 1e-14 of the correctly
+// rounded value, in about half the instructions of the IEEE square root and
+// division, and without a branch.  V = 0 (the node itself, or a coincident
+// node) takes |V| = 1 so that the factor stays finite and its product with
+// V is exactly zero.
 __device__ __forceinline__ double repulsion_factor(double r2, double C, double eta) {
   const double a = r2 > 0.0 ? r2 : 1.0;
   double y = __builtin_amdgcn_rsq(a);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {             // y <- y (3 - a y^2) / 2
-    const double e = fma(-(a * y), 0.5 * y, 0.5);
-    y = fma(y, e, y);
-  }
+  y = fma(y, fma(-(a * y), 0.5 * y, 0.5), y);      // y <- y (3 - a y^2) / 2
   const double L = a * y;
   const double den = a * L + eta;
   double r = __builtin_amdgcn_rcp(den);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {             // r <- r (2 - den r)
-    const double e = fma(-den, r, 1.0);
-    r = fma(r, e, r);
-  }
+  r = fma(r, fma(-den, r, 1.0), r);                // r <- r (2 - den r)
   const double q = C * r;
   return fma(fma(-den, q, C), r, q);
 }
