@@ -85,7 +85,7 @@ __global__ __launch_bounds__(1024) void scan_u32_kernel(uint32_t* v, int64_t cou
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t* keys_in, const uint32_t* vals_in, int64_t n, int shift, const uint32_t* offs,
     int nblk, uint32_t* keys_out, uint32_t* vals_out) {
-  __shared__ uint32_t wave_cnt[4][kDigits];   // keys per digit in each wave, this round
+  __shared__ uint32_t wave_cnt[4][kDigits];   // keys per digit in each wave, this pass
   __shared__ uint32_t running[kDigits];       // keys per digit in earlier rounds of this block
   __shared__ uint32_t wave_base[4][kDigits];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
