@@ -58,6 +58,8 @@ MUTATIONS = [
     ("layout temperature ignored", "  if (fl > t) {", "  if (fl > 1e300) {"),
     ("layout node-edge force reversed", "const double s = -C / (rx * rx + ry * ry + eta);",
      "const double s = C / (rx * rx + ry * ry + eta);"),
+    ("sampled layout step offsets the wrong node", "pos_out[2 * i] = pos_in[2 * v] + mv[0];",
+     "pos_out[2 * i] = pos_in[2 * i] + mv[0];"),
 ]
 
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_contour_pins.py",
