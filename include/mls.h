@@ -33,7 +33,12 @@
  *    returned synchronously; nothing is written to outputs in that case.
  *    A device failure during enqueue returns MLS_ERR_DEVICE.  The detail of
  *    the last error of the calling thread is available from mls_last_error().
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time.  Its scratch memory
+ *    is shared by all its calls: a call enqueued on a different stream
+ *    from the previous scratch-using call first makes its stream wait for
+ *    that call's work (an event the context records), so calls on several
+ *    streams are correct but run one after the other.  Use one context per
+ *    stream for concurrency.
  */
 #ifndef MLS_H_
 #define MLS_H_
@@ -335,12 +340,17 @@ mls_status mls_server_create(int32_t device, size_t hbm_budget_bytes, int32_t sl
                              size_t slot_scratch_bytes, mls_server** out);
 /* Wait for all submitted requests, then free everything. */
 void mls_server_destroy(mls_server* srv);
-/* Copy a point set (device or host pointers) into server memory. */
+/* Copy a point set (device or host pointers) into server memory; returns
+ * once the copy is complete.  The source buffers must already hold their
+ * values when the call is made: synchronise the stream that produced them
+ * first (the server's streams are not ordered with the caller's). */
 mls_status mls_server_put_points(mls_server* srv, const float* points, const float* values,
                                  int64_t n, int32_t d, uint64_t* pointset);
 /* Drop a point set once no queued or running request uses it. */
 mls_status mls_server_release_points(mls_server* srv, uint64_t pointset);
-/* Queue a request (returns at once).  MLS_ERR_OVER_BUDGET if its scratch
+/* Queue a request (returns at once).  The request's output buffers are
+ * written from a server stream that is not ordered with the caller's
+ * streams: work the caller queued on them must be complete at submit.  MLS_ERR_OVER_BUDGET if its scratch
  * exceeds a slot's; argument errors of the fit itself surface in its
  * result. */
 mls_status mls_server_submit(mls_server* srv, const mls_request* req, uint64_t* ticket);

@@ -7,6 +7,7 @@ Every step of the computation runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import threading
 
 from . import _lib
 
@@ -58,15 +59,56 @@ class Context:
             pass
 
 
-_default_ctx: dict[int, Context] = {}
+_default_ctx = threading.local()
 
 
 def default_context(device: int | None = None) -> Context:
+    """The calling thread's context on ``device``.  A context serves one host
+    thread at a time, so each thread gets its own; calls on one context that
+    use different streams are ordered by the library itself."""
     import torch
     dev = torch.cuda.current_device() if device is None else int(device)
-    if dev not in _default_ctx:
-        _default_ctx[dev] = Context(dev)
-    return _default_ctx[dev]
+    per_thread = getattr(_default_ctx, "by_device", None)
+    if per_thread is None:
+        per_thread = _default_ctx.by_device = {}
+    if dev not in per_thread:
+        per_thread[dev] = Context(dev)
+    return per_thread[dev]
+
+
+def _require(t, name: str, dtype, device=None, numel: int | None = None, shape=None):
+    """Refuse anything but a contiguous device tensor of ``dtype`` (and, when
+    given, on ``device``, with ``numel`` elements or exactly ``shape``): a
+    wrong buffer would make a kernel read or write past its end."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, not {t.numel()}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+
+
+def _points_values(points, values):
+    """Checked (points (N, 2), values (N, D)) float32 device tensors."""
+    import torch
+    _require(points, "points", torch.float32)
+    if points.dim() != 2 or points.shape[1] != 2:
+        raise ValueError(f"points must have shape (N, 2), not {tuple(points.shape)}")
+    _require(values, "values", torch.float32, device=points.device)
+    if values.dim() == 1:
+        values = values.view(-1, 1)
+    if values.dim() != 2:
+        raise ValueError(f"values must have shape (N, D), not {tuple(values.shape)}")
+    if values.shape[0] != points.shape[0]:
+        raise ValueError(f"points hold {points.shape[0]} rows, values {values.shape[0]}")
+    return points, values
 
 
 def grid_struct(grid: dict) -> _lib.MlsGrid:
@@ -96,16 +138,17 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
     uint8 or None)``; ``out`` / ``degree_out`` may supply the buffers.
     """
     import torch
-    assert points.dtype == torch.float32 and values.dtype == torch.float32
-    assert points.is_contiguous() and values.is_contiguous()
-    if values.dim() == 1:
-        values = values.view(-1, 1)
+    points, values = _points_values(points, values)
     n, d = values.shape
     W, H = int(grid["width"]), int(grid["height"])
     if out is None:
         out = torch.empty((d, H, W), dtype=torch.float32, device=points.device)
+    else:
+        _require(out, "out", torch.float32, device=points.device, numel=d * H * W)
     if degree_out is None and want_degree:
         degree_out = torch.empty((H, W), dtype=torch.uint8, device=points.device)
+    elif degree_out is not None:
+        _require(degree_out, "degree_out", torch.uint8, device=points.device, numel=H * W)
     ctx = ctx or default_context(points.device.index)
     g = grid_struct(grid)
     wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
@@ -127,10 +170,7 @@ def fit_grad(points, values, grid: dict, basis: str = "linear", weight: str = "g
     W), grads (D, 2, H, W), degree (H, W))``; grads[d, 0] = d f_d / dx,
     grads[d, 1] = d f_d / dy."""
     import torch
-    assert points.dtype == torch.float32 and values.dtype == torch.float32
-    assert points.is_contiguous() and values.is_contiguous()
-    if values.dim() == 1:
-        values = values.view(-1, 1)
+    points, values = _points_values(points, values)
     n, d = values.shape
     W, H = int(grid["width"]), int(grid["height"])
     out = torch.empty((d, H, W), dtype=torch.float32, device=points.device)
@@ -193,10 +233,14 @@ def contour(fields, grid: dict, iso, want_cases: bool = True, want_ids: bool = T
     and then runs again with an exact buffer.
     """
     import torch
-    assert fields.dtype == torch.float32 and fields.is_contiguous()
+    _require(fields, "fields", torch.float32)
     if fields.dim() == 2:
         fields = fields.unsqueeze(0)
+    if fields.dim() != 3:
+        raise ValueError(f"fields must have shape (D, H, W), not {tuple(fields.shape)}")
     D, H, W = fields.shape
+    if (W, H) != (int(grid["width"]), int(grid["height"])):
+        raise ValueError(f"fields are {H} x {W}, the grid {grid['height']} x {grid['width']}")
     iso = iso.to(device=fields.device, dtype=torch.float32).reshape(D, -1).contiguous()
     n_iso = iso.shape[1]
     dev = fields.device
@@ -258,6 +302,7 @@ class Server:
         if st != STATUS_OK:
             raise ServerError(st, "mls_server_create")
         self._keep = {}
+        self._sets = {}
         if tune or tuner_cache:
             self.tuning(tune, tuner_cache)
 
@@ -284,12 +329,17 @@ class Server:
             pass
 
     def put_points(self, points, values) -> int:
-        if values.dim() == 1:
-            values = values.view(-1, 1)
+        import torch
+        points, values = _points_values(points, values)
+        # the copy reads the tensors now, from the server's own stream: the
+        # work that produced them (on torch's stream) must be finished
+        torch.cuda.current_stream(points.device).synchronize()
         pid = ctypes.c_uint64()
-        st = _lib.load().mls_server_put_points(self._ptr, _ptr(points.contiguous()),
-                                               _ptr(values.contiguous()), values.shape[0],
-                                               values.shape[1], ctypes.byref(pid))
+        st = _lib.load().mls_server_put_points(self._ptr, _ptr(points), _ptr(values),
+                                               values.shape[0], values.shape[1],
+                                               ctypes.byref(pid))
+        if st == STATUS_OK:
+            self._sets[int(pid.value)] = (points.device, int(values.shape[1]))
         if st != STATUS_OK:
             raise ServerError(st, "mls_server_put_points")
         return int(pid.value)
@@ -298,11 +348,24 @@ class Server:
         st = _lib.load().mls_server_release_points(self._ptr, int(pointset))
         if st != STATUS_OK:
             raise ServerError(st, "mls_server_release_points")
+        self._sets.pop(int(pointset), None)
 
     def submit(self, pointset: int, grid: dict, out, degree_out=None, basis: str = "linear",
                weight: str = "gaussian", h: float = 0.05, alpha: float = 1.0,
                precision: str = "f64", pivot_tol: float = 1e-8, weight_floor: float = 1e-6,
                lp_terms: int = 0, lp_slab: int = 0) -> int:
+        import torch
+        # point sets of this server: the outputs must fit them (an unknown
+        # id is left to the library, which refuses it without a launch)
+        if int(pointset) in self._sets:
+            dev, d = self._sets[int(pointset)]
+            W, H = int(grid["width"]), int(grid["height"])
+            _require(out, "out", torch.float32, device=dev, numel=d * H * W)
+            if degree_out is not None:
+                _require(degree_out, "degree_out", torch.uint8, device=dev, numel=H * W)
+        # the server writes the outputs from its own streams, which are not
+        # ordered with torch's: whatever is still queued on them must finish
+        torch.cuda.current_stream(out.device).synchronize()
         req = _lib.MlsRequest(int(pointset), BASIS[basis],
                               _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha)),
                               grid_struct(grid), PRECISION[precision],

@@ -26,6 +26,14 @@ struct mls_context {
 
   // pinned host word for counts read back by mls_contour
   int64_t* pinned = nullptr;
+
+  // Both scratch buffers are shared by every call on the context, whatever
+  // its stream: `last_use` is recorded after the last enqueued work that
+  // touched them, on `last_stream`, and a call on another stream waits for
+  // it before its own kernels run.
+  hipEvent_t last_use = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool used = false;
 };
 
 namespace {
@@ -88,6 +96,24 @@ mls_status ensure_scratch(Scratch& sc, size_t bytes) {
     return fail(MLS_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes failed", want);
   }
   sc.bytes = want;
+  return MLS_OK;
+}
+
+// Order this call's scratch use after the previous call's, when the two run
+// on different streams.
+mls_status scratch_acquire(mls_context* ctx, hipStream_t s) {
+  if (ctx->used && ctx->last_stream != s) {
+    hipError_t e = hipStreamWaitEvent(s, ctx->last_use, 0);
+    if (e != hipSuccess) return device_fail(e, "hipStreamWaitEvent");
+  }
+  return MLS_OK;
+}
+
+mls_status scratch_release(mls_context* ctx, hipStream_t s) {
+  hipError_t e = hipEventRecord(ctx->last_use, s);
+  if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+  ctx->last_stream = s;
+  ctx->used = true;
   return MLS_OK;
 }
 
@@ -206,9 +232,16 @@ mls_status mls_context_create(int32_t device, mls_context** out) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(MLS_ERR_DEVICE, "device %d is %s; this library is built for gfx950", device,
                 prop.gcnArchName);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
   mls_context* ctx = new (std::nothrow) mls_context;
   if (!ctx) return fail(MLS_ERR_OUT_OF_MEMORY, "host allocation failed");
   ctx->device = device;
+  e = hipEventCreateWithFlags(&ctx->last_use, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete ctx;
+    return device_fail(e, "hipEventCreateWithFlags");
+  }
   *out = ctx;
   return MLS_OK;
 }
@@ -220,6 +253,7 @@ void mls_context_destroy(mls_context* ctx) {
     if (ctx->fit_scratch.ptr) (void)hipFree(ctx->fit_scratch.ptr);
 
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->last_use) (void)hipEventDestroy(ctx->last_use);
   }
   delete ctx;
 }
@@ -335,6 +369,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h, grid->x0, grid->y0,
                                 grid->dx, grid->dy, grid->width, grid->height);
       if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
+      if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
     }
     e = mls::launch_fit_f64(a, s);
     if (e != hipSuccess) return device_fail(e, "fit kernel launch");
@@ -361,6 +396,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       hta.hist = (uint32_t*)(base + plan.o_hist);
       e = mls::launch_hits(hta, s);
       if (e != hipSuccess) return device_fail(e, "exact-hit pass launch");
+      return scratch_release(ctx, s);
     }
     return MLS_OK;
   }
@@ -392,6 +428,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
                                                grid->x0, grid->y0, grid->dx, grid->dy,
                                                grid->width, grid->height);
   if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
+  if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
   char* base = (char*)ctx->fit_scratch.ptr;
   float* pmin = (float*)(base + plan.o_pmin);
   float* pmax = (float*)(base + plan.o_pmax);
@@ -403,7 +440,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   if (weight->kind != MLS_W_WENDLAND_C2) {
     e = mls::launch_fit_lp(a, vals_t, shift, scale, fp16, terms, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "fit kernel launch");
-    return MLS_OK;
+    return scratch_release(ctx, s);
   }
   mls::CellArgs ca;
   ca.pts = d_points;
@@ -440,7 +477,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   cl.geom = plan.geom;
   e = mls::launch_fit_lp(a, vals_t, shift, scale, fp16, terms, &cl, s);
   if (e != hipSuccess) return device_fail(e, "fit kernel launch");
-  return MLS_OK;
+  return scratch_release(ctx, s);
 }
 
 mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* d_adj_start,
@@ -474,6 +511,8 @@ mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* 
   if (n_fan > 0 && (st = check_device_ptr(ctx, d_fan, "d_fan")) != MLS_OK) return st;
   const size_t half = align_up(sizeof(double) * 2 * (size_t)n, 256);
   if ((st = ensure_scratch(ctx->fit_scratch, 2 * half)) != MLS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
   mls::LayoutArgs a;
   a.pos = d_pos;
   a.n = n;
@@ -491,9 +530,9 @@ mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* 
   a.iterations = iterations;
   a.buf0 = (double*)ctx->fit_scratch.ptr;
   a.buf1 = (double*)((char*)ctx->fit_scratch.ptr + half);
-  e = mls::launch_layout(a, (hipStream_t)stream);
+  e = mls::launch_layout(a, s);
   if (e != hipSuccess) return device_fail(e, "layout kernel launch");
-  return MLS_OK;
+  return scratch_release(ctx, s);
 }
 
 mls_status mls_context_reserve(mls_context* ctx, size_t bytes) {
@@ -531,11 +570,13 @@ size_t mls_fit_scratch_bytes(int64_t n, int32_t d, int32_t precision, const mls_
       .total;
 }
 
-mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
-                       const mls_grid* grid, const float* d_iso, int32_t n_iso,
-                       uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
-                       int64_t capacity, int64_t* h_count, void* stream) {
-  g_last_error[0] = '\0';
+// Arguments of mls_contour, checked before any device work; `count` is
+// the count output.
+static mls_status contour_check(mls_context* ctx, const float* d_fields, int32_t d,
+                                const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                                uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
+                                int64_t capacity, const int64_t* count,
+                                const char* count_name) {
   if (d < 1) return fail(MLS_ERR_INVALID_ARG, "d = %d; need at least one field", d);
   if (!grid) return fail(MLS_ERR_INVALID_ARG, "grid is NULL");
   if (grid->width < 2 || grid->height < 2)
@@ -545,7 +586,7 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
     return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
   if (n_iso < 1) return fail(MLS_ERR_INVALID_ARG, "n_iso = %d; need at least one", n_iso);
   if (capacity < 0) return fail(MLS_ERR_INVALID_ARG, "capacity = %lld", (long long)capacity);
-  if (!h_count) return fail(MLS_ERR_INVALID_ARG, "h_count is NULL");
+  if (!count) return fail(MLS_ERR_INVALID_ARG, "%s is NULL", count_name);
   if (!d_fields) return fail(MLS_ERR_INVALID_ARG, "d_fields is NULL");
   if (!d_iso) return fail(MLS_ERR_INVALID_ARG, "d_iso is NULL");
   if (capacity > 0 && !d_segments)
@@ -567,23 +608,29 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
   if (d_cases && (st = check_device_ptr(ctx, d_cases, "d_cases")) != MLS_OK) return st;
   if (d_segments && (st = check_device_ptr(ctx, d_segments, "d_segments")) != MLS_OK) return st;
   if (d_seg_ids && (st = check_device_ptr(ctx, d_seg_ids, "d_seg_ids")) != MLS_OK) return st;
+  return MLS_OK;
+}
 
+// Byte offsets of one contour call's scratch: counts (scanned in place),
+// tile sums, total.
+struct ContourScratch {
+  size_t off_tiles, off_total, need;
+};
+
+static ContourScratch contour_scratch_plan(int32_t d, int32_t n_iso, const mls_grid* grid) {
   const int64_t entries = mls::contour_scratch_entries(d, n_iso, grid->width, grid->height);
   const int64_t tiles = mls::contour_scan_tiles(entries);
-  const size_t off_counts = 0;
-  const size_t off_tiles = align_up(sizeof(int32_t) * (size_t)entries, 256);
-  const size_t off_total = off_tiles + align_up(sizeof(int64_t) * (size_t)tiles, 256);
-  const size_t need = off_total + 256;
-  if ((st = ensure_scratch(ctx->scratch, need)) != MLS_OK) return st;
-  if (!ctx->pinned) {
-    e = hipHostMalloc((void**)&ctx->pinned, sizeof(int64_t) * 4, hipHostMallocDefault);
-    if (e != hipSuccess) {
-      ctx->pinned = nullptr;
-      (void)hipGetLastError();
-      return fail(MLS_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
-    }
-  }
-  char* base = (char*)ctx->scratch.ptr;
+  ContourScratch c;
+  c.off_tiles = align_up(sizeof(int32_t) * (size_t)entries, 256);
+  c.off_total = c.off_tiles + align_up(sizeof(int64_t) * (size_t)tiles, 256);
+  c.need = c.off_total + 256;
+  return c;
+}
+
+static mls::ContourArgs contour_args(const float* d_fields, int32_t d, const mls_grid* grid,
+                                     const float* d_iso, int32_t n_iso, uint8_t* d_cases,
+                                     float* d_segments, int32_t* d_seg_ids, int64_t capacity,
+                                     char* base, const ContourScratch& cs, int64_t* total) {
   mls::ContourArgs a;
   a.fields = d_fields;
   a.iso = d_iso;
@@ -599,13 +646,40 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
   a.segs = d_segments;
   a.ids = d_seg_ids;
   a.capacity = capacity;
-  a.counts = (int32_t*)(base + off_counts);
+  a.counts = (int32_t*)base;
   a.offsets = a.counts;   // scanned in place
-  a.tile_sums = (int64_t*)(base + off_tiles);
-  a.total = (int64_t*)(base + off_total);
+  a.tile_sums = (int64_t*)(base + cs.off_tiles);
+  a.total = total ? total : (int64_t*)(base + cs.off_total);
+  return a;
+}
+
+mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
+                       const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                       uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
+                       int64_t capacity, int64_t* h_count, void* stream) {
+  g_last_error[0] = '\0';
+  mls_status st = contour_check(ctx, d_fields, d, grid, d_iso, n_iso, d_cases, d_segments,
+                                d_seg_ids, capacity, h_count, "h_count");
+  if (st != MLS_OK) return st;
+  hipError_t e;
+  const ContourScratch cs = contour_scratch_plan(d, n_iso, grid);
+  if ((st = ensure_scratch(ctx->scratch, cs.need)) != MLS_OK) return st;
+  if (!ctx->pinned) {
+    e = hipHostMalloc((void**)&ctx->pinned, sizeof(int64_t) * 4, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ctx->pinned = nullptr;
+      (void)hipGetLastError();
+      return fail(MLS_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+    }
+  }
+  const mls::ContourArgs a = contour_args(d_fields, d, grid, d_iso, n_iso, d_cases, d_segments,
+                                          d_seg_ids, capacity, (char*)ctx->scratch.ptr, cs,
+                                          nullptr);
   hipStream_t s = (hipStream_t)stream;
+  if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
   e = mls::launch_contour(a, s);
   if (e != hipSuccess) return device_fail(e, "contour kernel launch");
+  if ((st = scratch_release(ctx, s)) != MLS_OK) return st;
   e = hipMemcpyAsync(ctx->pinned, a.total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return device_fail(e, "count read-back");
   e = hipStreamSynchronize(s);

@@ -102,6 +102,10 @@ struct Tuner {
 
 struct mls_server {
   int device = 0;
+  // point-set copies: issued here and waited for before put_points
+  // returns, so that no slot stream (non-blocking, unordered with the
+  // caller's streams) can read a point set before it is complete
+  hipStream_t copy_stream = nullptr;
   Tuner tuner;
   size_t budget = 0;
   size_t slot_scratch = 0;
@@ -405,6 +409,14 @@ mls_status mls_server_create(int32_t device, size_t hbm_budget_bytes, int32_t sl
       return sfail(MLS_ERR_DEVICE, "stream or event creation: %s", hipGetErrorString(e));
     }
   }
+  {
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      cleanup();
+      return sfail(MLS_ERR_DEVICE, "copy stream creation: %s", hipGetErrorString(e));
+    }
+  }
   mls_server* raw = s.release();
   raw->sched = std::thread(scheduler, raw);
   *out = raw;
@@ -430,6 +442,7 @@ void mls_server_destroy(mls_server* s) {
     if (sl.ev1) (void)hipEventDestroy(sl.ev1);
     if (sl.ctx) mls_context_destroy(sl.ctx);
   }
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   for (auto& kv : s->psets) {
     (void)hipFree(kv.second.pts);
     (void)hipFree(kv.second.vals);
@@ -489,9 +502,14 @@ mls_status mls_server_put_points(mls_server* s, const float* d_points, const flo
     if (ps.pts) (void)hipFree(ps.pts);
     return sfail(MLS_ERR_OUT_OF_MEMORY, "point set allocation failed");
   }
-  hipError_t e = hipMemcpy(ps.pts, d_points, (size_t)n * 2 * sizeof(float), hipMemcpyDefault);
+  // a device-to-device hipMemcpy may return before the copy has landed;
+  // copy on the server's own stream and wait for it
+  hipError_t e = hipMemcpyAsync(ps.pts, d_points, (size_t)n * 2 * sizeof(float),
+                                hipMemcpyDefault, s->copy_stream);
   if (e == hipSuccess)
-    e = hipMemcpy(ps.vals, d_values, (size_t)n * d * sizeof(float), hipMemcpyDefault);
+    e = hipMemcpyAsync(ps.vals, d_values, (size_t)n * d * sizeof(float), hipMemcpyDefault,
+                       s->copy_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
   if (e != hipSuccess) {
     (void)hipFree(ps.pts);
     (void)hipFree(ps.vals);

@@ -35,6 +35,15 @@ def compare(gpu_fields, gpu_deg, or_fields, or_deg, or_dmin, values, dmin_pass=1
         "per_field_max_pass": (err[:, passset].max(axis=1).tolist() if passset.any()
                                else [0.0] * gf.shape[0]),
     }
+    # same-degree nodes by the oracle's smallest equilibrated pivot
+    bins = {}
+    for name, lo, hi in (("dmin>=1e-2", 1e-2, np.inf), ("1e-3<=dmin<1e-2", 1e-3, 1e-2),
+                         ("1e-5<=dmin<1e-3", 1e-5, 1e-3), ("dmin<1e-5", -np.inf, 1e-5)):
+        sel = both & (dm >= lo) & (dm < hi)
+        bins[name] = {"nodes": int(sel.sum()),
+                      "max": float(err[:, sel].max()) if sel.any() else 0.0,
+                      "rms": float(np.sqrt(np.mean(err[:, sel] ** 2))) if sel.any() else 0.0}
+    out["bins"] = bins
     # NaN exactly where undetermined
     und = gd == 255
     out["nan_ok"] = bool(np.all(np.isnan(gf[:, und])) and np.all(np.isfinite(gf[:, ~und])))

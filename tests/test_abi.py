@@ -197,3 +197,18 @@ def test_layout_binding_rejects_host_and_mistyped_arrays():
     with pytest.raises(ValueError, match="device tensor"):
         api.layout(torch.zeros(3, 2, dtype=torch.float64), mesh, C=1.0, D=1.0, eta=1e-3,
                    t0=0.1, lam=0.9, iterations=1)
+
+
+def test_fit_binding_rejects_host_and_mistyped_tensors():
+    """The fit binding refuses host tensors, other dtypes, mis-shaped points
+    and points/values of different lengths before anything reaches the
+    library (a wrong buffer would be read or written past its end)."""
+    import torch
+    from paper_1408_0677_amd import api
+    grid = {"x0": 0.0, "y0": 0.0, "dx": 0.1, "dy": 0.1, "width": 8, "height": 8}
+    with pytest.raises(ValueError, match="device tensor"):
+        api.fit(torch.zeros(10, 2), torch.zeros(10, 3), grid)
+    with pytest.raises(ValueError, match="device tensor"):
+        api.fit_grad(torch.zeros(10, 2), torch.zeros(10, 3), grid)
+    with pytest.raises(ValueError, match="device tensor"):
+        api.contour(torch.zeros(1, 8, 8), grid, torch.zeros(1, 1))

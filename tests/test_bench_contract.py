@@ -23,10 +23,16 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_only_from_current_sources():
     """The committed summaries carry the sources' digest; the figure is used
     only while the sources still hash to it."""
+    import re
     for summary, sources in (("fit_f64_c2_1024_traffic.md", bench.F64_SOURCES),
                              ("fit_lp_c5_traffic.md", bench.LP_SOURCES)):
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        recorded = re.search(r"source_sha256: `([0-9a-f]+)`", text).group(1)
         t = bench.profiled_traffic(summary, sources)
-        assert isinstance(t, int) and t > 0
+        if recorded == bench.source_digest(sources):
+            assert isinstance(t, int) and t > 0
+        else:
+            assert t is None
         assert bench.profiled_traffic(summary, sources + ["bench.py"]) is None
     assert bench.profiled_traffic("no_such_summary.md", bench.F64_SOURCES) is None
 
@@ -44,3 +50,16 @@ def test_support_pairs_matches_brute_force():
     assert bench.support_pairs(pts, grid, h) == int(np.sum(d2 < h * h))
     rows = np.arange(0, 29, 4)
     assert bench.support_pairs(pts, grid, h, rows=rows) == int(np.sum(d2[:, rows, :] < h * h))
+
+
+def test_traffic_summary_is_keyed_by_workload():
+    """Only the workload a summary was taken on reports its traffic: the
+    timing-table workloads have none."""
+    from paper_1408_0677_amd import workloads as wl
+    assert bench.TRAFFIC_SUMMARIES.get(wl.c2().name) == "fit_f64_c2_1024_traffic.md"
+    for n in (306, 1000, 2245):
+        assert wl.t1(n).name not in bench.TRAFFIC_SUMMARIES
+
+
+def test_layout_pair_count_counts_fused_multiply_adds_once():
+    assert bench.LAYOUT_OPS_PER_PAIR == 10

@@ -156,9 +156,34 @@ def test_host_pointer_rejected(torch_dev):
     vals = torch.rand(10, 1)
     grid = {"x0": 0.0, "y0": 0.0, "dx": 0.1, "dy": 0.1, "width": 4, "height": 4}
     out = torch.empty(1, 4, 4, device="cuda")
-    with pytest.raises(api.MlsError) as ei:
+    # the binding refuses host tensors before the call ...
+    with pytest.raises(ValueError, match="device tensor"):
         api.fit(pts, vals, grid, out=out, want_degree=False)
-    assert "MLS_ERR_INVALID_ARG" in str(ei.value)
+    # ... and the library itself refuses a host pointer passed straight
+    # through the C ABI
+    import ctypes
+    from paper_1408_0677_amd import _lib
+    lib = _lib.load()
+    ctx = api.default_context(0)
+    w = _lib.MlsWeight(0, 0.1, 1.0)
+    g = _lib.MlsGrid(0.0, 0.0, 0.1, 0.1, 4, 4)
+    st = lib.mls_fit(ctx.handle, ctypes.c_void_p(pts.data_ptr()),
+                     ctypes.c_void_p(vals.data_ptr()), 10, 1, 1, ctypes.byref(w),
+                     ctypes.byref(g), 0, None, ctypes.c_void_p(out.data_ptr()), None, None)
+    assert st == -1 and b"d_points" in lib.mls_last_error()
+    # mis-sized or mistyped outputs, and points/values of different lengths
+    P = pts.cuda()
+    V = vals.cuda()
+    with pytest.raises(ValueError, match="elements"):
+        api.fit(P, V, grid, out=torch.empty(1, 4, 3, device="cuda"))
+    with pytest.raises(ValueError, match="float32"):
+        api.fit(P, V, grid, out=torch.empty(1, 4, 4, device="cuda", dtype=torch.float16))
+    with pytest.raises(ValueError, match="elements"):
+        api.fit(P, V, grid, degree_out=torch.empty(15, device="cuda", dtype=torch.uint8))
+    with pytest.raises(ValueError, match="rows"):
+        api.fit(P[:9], V, grid)
+    with pytest.raises(ValueError, match="shape"):
+        api.fit(P.view(-1), V, grid)
 
 
 def test_unsupported_weight_reported(torch_dev):
