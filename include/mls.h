@@ -300,6 +300,33 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
                        uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
                        int64_t capacity, int64_t* h_count, void* stream);
 
+/*
+ * Allocation-free variant of mls_contour, for callers that cannot allocate
+ * device or pinned memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same segments,
+ * ids and cases as mls_contour, bit for bit, with three differences:
+ *  - the scratch is a fixed device array of MLS_CONTOUR_STATIC_SCRATCH_BYTES
+ *    per GPU, held from the first context created on the GPU until the
+ *    process ends; a call needs 4 (d n_iso chunks) + 8 tiles + 256 bytes of
+ *    it, where chunks = ceil((height-1)(width-1) / 256) and tiles =
+ *    ceil(d n_iso chunks / 1024), and returns MLS_ERR_INVALID_ARG for
+ *    larger calls before enqueueing anything;
+ *  - the required segment count goes to d_count, an int64 in device
+ *    memory, written by the stream; the call does not wait for the stream;
+ *  - when the count exceeds capacity, the first `capacity` segments (and
+ *    ids) are still written, in order.
+ * Every call on one GPU shares that GPU's array and overwrites what the
+ * last call left there: calls that overlap on one GPU (other streams,
+ * other threads, other contexts) race and must be ordered by the caller.
+ * Nothing needs clearing between calls.  The context only names the device
+ * (its own scratch is not used).
+ */
+#define MLS_CONTOUR_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+mls_status mls_contour_static(mls_context* ctx, const float* d_fields, int32_t d,
+                              const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                              uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
+                              int64_t capacity, int64_t* d_count, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Served form: resident point sets and continuously batched fit requests    */
 /* ------------------------------------------------------------------------ */

@@ -14,12 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MLS_HIP_LIB") or os.path.join(HERE, "libmls_hip.so")
 
 # Symbols declared in include/mls.h.
+CONTOUR_STATIC_SCRATCH_BYTES = 16 << 20   # MLS_CONTOUR_STATIC_SCRATCH_BYTES
 EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_context_destroy", "mls_fit", "mls_contour", "mls_fit_scratch_bytes",
            "mls_context_reserve", "mls_server_create", "mls_server_destroy",
            "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
            "mls_server_poll", "mls_server_wait", "mls_server_last_error",
-           "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad", "mls_layout")
+           "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad", "mls_layout",
+           "mls_contour_static")
 
 
 class MlsGrid(ctypes.Structure):
@@ -92,6 +94,9 @@ def load():
     lib.mls_contour.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P, i64,
                                 ctypes.POINTER(i64), P]
     lib.mls_contour.restype = ctypes.c_int
+    lib.mls_contour_static.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P,
+                                       i64, P, P]
+    lib.mls_contour_static.restype = ctypes.c_int
     lib.mls_fit_scratch_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(MlsWeight),
                                           ctypes.POINTER(MlsGrid)]
     lib.mls_fit_scratch_bytes.restype = ctypes.c_size_t

@@ -267,6 +267,47 @@ def contour(fields, grid: dict, iso, want_cases: bool = True, want_ids: bool = T
     return segs[:n], (ids[:n] if ids is not None else None), cases
 
 
+def contour_static(fields, grid: dict, iso, segments, count, ids=None, cases=None,
+                   ctx: Context | None = None, stream=None):
+    """Allocation-free marching squares (mls_contour_static) into caller
+    buffers: ``segments`` float32 (capacity, 4), ``count`` int64 (1,) device
+    tensor receiving the required segment count, optional ``ids`` int32
+    (capacity, 3) and ``cases`` uint8 (D, n_iso, H-1, W-1).  Returns at once;
+    the first min(count, capacity) segments are valid once the stream has
+    run."""
+    import torch
+    _require(fields, "fields", torch.float32)
+    if fields.dim() == 2:
+        fields = fields.unsqueeze(0)
+    if fields.dim() != 3:
+        raise ValueError(f"fields must have shape (D, H, W), not {tuple(fields.shape)}")
+    D, H, W = fields.shape
+    if (W, H) != (int(grid["width"]), int(grid["height"])):
+        raise ValueError(f"fields are {H} x {W}, the grid {grid['height']} x {grid['width']}")
+    dev = fields.device
+    _require(iso, "iso", torch.float32, device=dev)
+    if iso.numel() % D or iso.numel() == 0:
+        raise ValueError("iso must hold n_iso values per field")
+    n_iso = iso.numel() // D
+    _require(segments, "segments", torch.float32, device=dev)
+    if segments.dim() != 2 or segments.shape[1] != 4:
+        raise ValueError("segments must have shape (capacity, 4)")
+    cap = int(segments.shape[0])
+    _require(count, "count", torch.int64, device=dev, numel=1)
+    if ids is not None:
+        _require(ids, "ids", torch.int32, device=dev, numel=3 * cap)
+    if cases is not None:
+        _require(cases, "cases", torch.uint8, device=dev, numel=D * n_iso * (H - 1) * (W - 1))
+    ctx = ctx or default_context(dev.index)
+    g = grid_struct(grid)
+    st = _lib.load().mls_contour_static(ctx.handle, _ptr(fields), D, ctypes.byref(g), _ptr(iso),
+                                        n_iso, _ptr(cases), _ptr(segments) if cap else None,
+                                        _ptr(ids) if cap else None, cap, _ptr(count),
+                                        _stream_handle(stream))
+    _check(st, "mls_contour_static")
+    return segments, count
+
+
 PENDING = 1
 
 

@@ -242,6 +242,13 @@ mls_status mls_context_create(int32_t device, mls_context** out) {
     delete ctx;
     return device_fail(e, "hipEventCreateWithFlags");
   }
+  // the fixed scratch of mls_contour_static: its address on this device
+  e = mls::contour_static_scratch_resolve(device);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ctx->last_use);
+    delete ctx;
+    return device_fail(e, "hipGetSymbolAddress (contour scratch)");
+  }
   *out = ctx;
   return MLS_OK;
 }
@@ -570,8 +577,8 @@ size_t mls_fit_scratch_bytes(int64_t n, int32_t d, int32_t precision, const mls_
       .total;
 }
 
-// Arguments of mls_contour, checked before any device work; `count` is
-// the count output.
+// Arguments of mls_contour / mls_contour_static, checked before any device
+// work; `count` is h_count or d_count.
 static mls_status contour_check(mls_context* ctx, const float* d_fields, int32_t d,
                                 const mls_grid* grid, const float* d_iso, int32_t n_iso,
                                 uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
@@ -688,6 +695,32 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
   if (*h_count > capacity)
     return fail(MLS_ERR_CAPACITY, "%lld segments, capacity %lld", (long long)*h_count,
                 (long long)capacity);
+  return MLS_OK;
+}
+
+mls_status mls_contour_static(mls_context* ctx, const float* d_fields, int32_t d,
+                              const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                              uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
+                              int64_t capacity, int64_t* d_count, void* stream) {
+  g_last_error[0] = '\0';
+  mls_status st = contour_check(ctx, d_fields, d, grid, d_iso, n_iso, d_cases, d_segments,
+                                d_seg_ids, capacity, d_count, "d_count");
+  if (st != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_count, "d_count")) != MLS_OK) return st;
+  if (((uintptr_t)d_count % 8) != 0) return fail(MLS_ERR_INVALID_ARG, "d_count must be 8-byte aligned");
+  const ContourScratch cs = contour_scratch_plan(d, n_iso, grid);
+  if (cs.need > MLS_CONTOUR_STATIC_SCRATCH_BYTES)
+    return fail(MLS_ERR_INVALID_ARG, "%d fields x %d isovalues on %d x %d nodes need %zu bytes "
+                "of contour scratch; the static scratch holds %zu", d, n_iso, grid->width,
+                grid->height, cs.need, (size_t)MLS_CONTOUR_STATIC_SCRATCH_BYTES);
+  // the address resolved for this device when the context was created
+  char* base = (char*)mls::contour_static_scratch(ctx->device);
+  if (!base) return fail(MLS_ERR_DEVICE, "static contour scratch not resolved on device %d",
+                         ctx->device);
+  const mls::ContourArgs a = contour_args(d_fields, d, grid, d_iso, n_iso, d_cases, d_segments,
+                                          d_seg_ids, capacity, base, cs, d_count);
+  hipError_t e = mls::launch_contour(a, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "contour kernel launch");
   return MLS_OK;
 }
 

@@ -29,6 +29,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
+#include "../../include/mls.h"
 #include "mls_internal.h"
 
 namespace mls {
@@ -371,7 +374,35 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(Conto
   }
 }
 
+// Fixed scratch of the allocation-free contour entry point: counts,
+// offsets and tile sums of one call, MLS_CONTOUR_STATIC_SCRATCH_BYTES in
+// all.  Each device holds its own copy for the life of the process.  In
+// host code the name stands for a host-side handle only: kernels get the
+// device address that contour_static_scratch_resolve() looks up.
+static __device__ __align__(256) char scratch[MLS_CONTOUR_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+hipError_t contour_static_scratch_resolve(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* contour_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  return g_scratch_ptr[device];
+}
 
 int64_t contour_scratch_entries(int32_t D, int32_t n_iso, int32_t W, int32_t H) {
   const int64_t cells = (int64_t)(W - 1) * (H - 1);

@@ -184,6 +184,12 @@ int64_t contour_scratch_entries(int32_t D, int32_t n_iso, int32_t W, int32_t H);
 int64_t contour_scan_tiles(int64_t entries);
 hipError_t launch_contour(const ContourArgs& a, hipStream_t stream);
 
+// The contour passes' fixed device scratch (for callers that cannot
+// allocate): resolve its address on `device` (made current by the caller;
+// once per device, later calls return the cached address), and read it back.
+hipError_t contour_static_scratch_resolve(int device);
+void* contour_static_scratch(int device);
+
 // Planarity-preserving layout iterations (float64 state in buf0/buf1,
 // each [n][2]); pos holds the float32 positions in and out.
 struct LayoutArgs {

@@ -212,3 +212,20 @@ def test_fit_binding_rejects_host_and_mistyped_tensors():
         api.fit_grad(torch.zeros(10, 2), torch.zeros(10, 3), grid)
     with pytest.raises(ValueError, match="device tensor"):
         api.contour(torch.zeros(1, 8, 8), grid, torch.zeros(1, 1))
+
+
+def test_contour_static_arguments_rejected_before_device(lib):
+    """The allocation-free contour shares mls_contour's checks; it names its
+    device count output."""
+    from paper_1408_0677_amd import _lib
+    g = _lib.MlsGrid(0.0, 0.0, 0.1, 0.1, 8, 8)
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.mls_contour_static(None, fake, 1, ctypes.byref(g), fake, 2, None, fake, None, 10,
+                                None, None)
+    assert st == -1 and b"d_count is NULL" in lib.mls_last_error()
+    st = lib.mls_contour_static(None, fake, 1, ctypes.byref(g), fake, 0, None, fake, None, 10,
+                                fake, None)
+    assert st == -1 and b"n_iso = 0" in lib.mls_last_error()
+    st = lib.mls_contour_static(None, fake, 1, ctypes.byref(g), fake, 2, None, fake, None, 10,
+                                fake, None)
+    assert st == -1 and b"ctx is NULL" in lib.mls_last_error()
