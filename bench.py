@@ -309,6 +309,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--latency-fits", type=int, default=0,
+                    help="single fits behind the p50/p99 fit latency (default: 100, "
+                         "fewer where 100 would take over 20 s)")
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c3", "c4", "c5", "t1", "layout"],
                     help="c2: the 1024^2 float64 fit + contour step (default); c3: the "
@@ -447,8 +450,9 @@ def fit_step_bench(args, w, prec):
 
     # fit latency over single fits, each bracketed by events on the launch
     # stream (at least 100, fewer only where 100 would take over 20 s)
-    n_lat = 100 if float(np.mean(fit_ms)) * 100 <= 20e3 else max(
-        args.steps, int(20e3 / float(np.mean(fit_ms))))
+    n_lat = args.latency_fits if args.latency_fits > 0 else (
+        100 if float(np.mean(fit_ms)) * 100 <= 20e3 else max(
+            args.steps, int(20e3 / float(np.mean(fit_ms)))))
     lat_ms = []
     for _ in range(n_lat):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -187,6 +187,9 @@ FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, do
     p.o_to = carve(4 * (size_t)p.tiles);
     p.o_to2 = carve(4 * (size_t)p.tiles);
     p.o_th = carve(4 * 256 * (size_t)trb);
+    p.o_ts = carve(4 * (size_t)(p.tiles + 1));
+    p.list_cap = tile_list_bound(n, h, dx, dy, p.tiles_x, p.tiles / p.tiles_x);
+    p.o_tl = carve(4 * (size_t)p.list_cap);
   }
   p.total = off;
   return p;
@@ -434,6 +437,9 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   const mls::FitPlan plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h,
                                                grid->x0, grid->y0, grid->dx, grid->dy,
                                                grid->width, grid->height);
+  if (weight->kind == MLS_W_WENDLAND_C2 && plan.list_cap > (int64_t)0xFFFFFFFFu)
+    return fail(MLS_ERR_UNSUPPORTED, "the per-tile point lists of %lld points with h = %g on "
+                "this grid could exceed 2^32 entries", (long long)n, weight->h);
   if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
   if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
   char* base = (char*)ctx->fit_scratch.ptr;
@@ -472,6 +478,9 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   ca.tkeys2 = (uint32_t*)(base + plan.o_tk2);
   ca.torder2 = (uint32_t*)(base + plan.o_to2);
   ca.thist = (uint32_t*)(base + plan.o_th);
+  ca.tile_start = (uint32_t*)(base + plan.o_ts);
+  ca.tile_list = (uint32_t*)(base + plan.o_tl);
+  ca.list_cap = plan.list_cap;
   e = mls::launch_cells(ca, s);
   if (e != hipSuccess) return device_fail(e, "cell list kernels");
   mls::LPCells cl;
@@ -479,6 +488,8 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   cl.vals_ts = ca.vals_ts;
   cl.cell_start = ca.cell_start;
   cl.torder = ca.torder;
+  cl.tile_start = ca.tile_start;
+  cl.tile_list = ca.tile_list;
   cl.ncx = plan.ncx;
   cl.ncy = plan.ncy;
   cl.geom = plan.geom;

@@ -14,9 +14,12 @@
 //              ballots and per-wave digit counts in LDS,
 // so points of one cell keep their input order and every run produces the
 // same payload.  Then per-cell counts (cell_start by exclusive scan) and a
-// gather of coordinates and normalised attributes into cell order.  A
-// second sort orders node tiles by descending work (points in their support
-// cells) so that the heavy tiles of dense clusters start first.
+// gather of coordinates and normalised attributes into cell order.  Then
+// per node tile the list of points within h of its nodes (from the cells
+// the tile's support reaches, so a tile's fit touches no point that cannot
+// weigh in; the cells alone hold 2-4x more), and a second sort that orders
+// node tiles by descending list length, so that the heavy tiles of dense
+// clusters start first.
 // All of it is bound by HBM and launch latency, not arithmetic.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -176,26 +179,83 @@ __global__ __launch_bounds__(256) void gather_values_kernel(const float* vals_t,
   vals_ts[(int64_t)d * n + i] = vals_t[(int64_t)d * n + perm[i]];
 }
 
-// Work of each node tile: points in the cells its support can reach.  The
-// key sorts tiles by descending work (stable, so equal work keeps tile
-// order).
-__global__ __launch_bounds__(256) void tile_cost_kernel(const uint32_t* cell_start, int ncx,
-                                                        int ncy, CellGeom g, int tiles_x,
-                                                        int tiles, uint32_t* keys,
-                                                        uint32_t* idx) {
-  const int tile = blockIdx.x * 256 + threadIdx.x;
-  if (tile >= tiles) return;
+__global__ __launch_bounds__(256) void iota_u32_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
+// Per-tile point lists.  One wave per node tile walks the cell runs the
+// tile's support can reach and keeps the points within h of the tile's
+// node rectangle (a point farther than that has zero weight at every node
+// of the tile), in cell order.  Count pass (list == null): the number of
+// such points goes to counts[tile] and, as a descending-work sort key, to
+// keys[tile].  Fill pass: the indices are written from tile_start[tile] on.
+// The test runs in float64 with a relative margin of 1e-4 on h^2, so that
+// a point the fit kernel's float32 distance could still place inside the
+// support is never dropped; the extra points get zero weight there.
+__global__ __launch_bounds__(256) void tile_list_kernel(const uint32_t* cell_start,
+                                                        const float* pts_s, int ncx, int ncy,
+                                                        CellGeom g, int tiles_x, int tiles,
+                                                        uint32_t* counts, uint32_t* keys,
+                                                        const uint32_t* tile_start,
+                                                        uint32_t* list, int64_t list_cap) {
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= tiles) return;   // whole wave; no barrier below
+  const int tc = tile % tiles_x, tr = tile / tiles_x;
   int cx0, cx1, cy0, cy1;
-  tile_cell_range(g, tile % tiles_x, tile / tiles_x, ncx, ncy, &cx0, &cx1, &cy0, &cy1);
-  uint64_t work = 0;
-  for (int cy = cy0; cy <= cy1; ++cy)
-    work += cell_start[cy * ncx + cx1 + 1] - cell_start[cy * ncx + cx0];
-  const uint32_t w = work > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)work;
-  keys[tile] = 0xFFFFFFFFu - w;
-  idx[tile] = (uint32_t)tile;
+  tile_cell_range(g, tc, tr, ncx, ncy, &cx0, &cx1, &cy0, &cy1);
+  const double xa = g.x0 + (double)(tc * kTileCols) * g.dx;
+  const double xb = g.x0 + (double)(tc * kTileCols + kTileCols - 1) * g.dx;
+  const double ya = g.y0 + (double)(tr * kTileRows) * g.dy;
+  const double yb = g.y0 + (double)(tr * kTileRows + kTileRows - 1) * g.dy;
+  const double xlo = fmin(xa, xb), xhi = fmax(xa, xb), ylo = fmin(ya, yb), yhi = fmax(ya, yb);
+  const double reach2 = g.h * g.h * (1.0 + 1e-4);
+  const uint64_t below = (1ull << lane) - 1ull;
+  int64_t out = list ? (int64_t)tile_start[tile] : 0;
+  uint32_t cnt = 0;
+  for (int cy = cy0; cy <= cy1; ++cy) {
+    const int64_t a = cell_start[cy * ncx + cx0];
+    const int64_t b = cell_start[cy * ncx + cx1 + 1];
+    for (int64_t k0 = a; k0 < b; k0 += 64) {
+      const int64_t k = k0 + lane;
+      bool in = false;
+      if (k < b) {
+        const double x = (double)pts_s[2 * k], y = (double)pts_s[2 * k + 1];
+        const double ex = fmax(fmax(xlo - x, x - xhi), 0.0);
+        const double ey = fmax(fmax(ylo - y, y - yhi), 0.0);
+        in = ex * ex + ey * ey < reach2;
+      }
+      const uint64_t m = __ballot(in);
+      if (list && in) {
+        const int64_t o = out + __popcll(m & below);
+        if (o < list_cap) list[o] = (uint32_t)k;
+      }
+      out += __popcll(m);
+      cnt += (uint32_t)__popcll(m);
+    }
+  }
+  if (!list && lane == 0) {
+    counts[tile] = cnt;
+    keys[tile] = 0xFFFFFFFFu - cnt;
+  }
 }
 
 }  // namespace
+
+int64_t tile_list_bound(int64_t n, double h, double dx, double dy, int tiles_x, int tiles_y) {
+  // a point is listed by tile t when it lies within h of t's node
+  // rectangle: along x that is a window of 2 h + 15 |dx| for the tiles'
+  // first nodes, which are 16 |dx| apart (likewise along y)
+  const double hh = h * 1.0001;
+  auto per_axis = [&](double d, int tiles) -> int64_t {
+    const double w = 16.0 * fabs(d);
+    if (!(w > 0.0)) return tiles;
+    const double k = floor((2.0 * hh + w) / w) + 1.0;
+    return k < (double)tiles ? (int64_t)k : (int64_t)tiles;
+  };
+  return n * per_axis(dx, tiles_x) * per_axis(dy, tiles_y);
+}
 
 int64_t radix_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
@@ -242,10 +302,21 @@ hipError_t launch_cells(const CellArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(gather_points_kernel, dim3(gb), dim3(256), 0, s, a.pts, a.perm, n, a.pts_s);
   hipLaunchKernelGGL(gather_values_kernel, dim3(gb, a.D), dim3(256), 0, s, a.vals_t, a.perm, n,
                      a.D, a.vals_ts);
-  // tile order by descending work
+  // per-tile point lists: counts (and the work keys), starts, entries
+  const unsigned lb = (unsigned)((a.tiles + 3) / 4);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((a.tiles + 1 + 255) / 256)), dim3(256), 0,
+                     s, a.tile_start, (int64_t)a.tiles + 1, 0u);
+  hipLaunchKernelGGL(tile_list_kernel, dim3(lb), dim3(256), 0, s, a.cell_start, a.pts_s, a.ncx,
+                     a.ncy, a.geom, a.tiles_x, a.tiles, a.tile_start, a.tkeys,
+                     (const uint32_t*)nullptr, (uint32_t*)nullptr, (int64_t)0);
+  hipLaunchKernelGGL(scan_u32_kernel, dim3(1), dim3(1024), 0, s, a.tile_start,
+                     (int64_t)a.tiles + 1, (uint32_t*)nullptr);
+  hipLaunchKernelGGL(tile_list_kernel, dim3(lb), dim3(256), 0, s, a.cell_start, a.pts_s, a.ncx,
+                     a.ncy, a.geom, a.tiles_x, a.tiles, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                     (const uint32_t*)a.tile_start, a.tile_list, a.list_cap);
+  // tile order by descending work (list length)
   const int tb = (a.tiles + 255) / 256;
-  hipLaunchKernelGGL(tile_cost_kernel, dim3(tb), dim3(256), 0, s, a.cell_start, a.ncx, a.ncy,
-                     a.geom, a.tiles_x, a.tiles, a.tkeys, a.torder);
+  hipLaunchKernelGGL(iota_u32_kernel, dim3(tb), dim3(256), 0, s, a.torder, (int64_t)a.tiles);
   e = radix_sort_pairs(a.tkeys, a.torder, a.tkeys2, a.torder2, a.tiles, 32, a.thist, s);
   return e != hipSuccess ? e : hipGetLastError();
 }

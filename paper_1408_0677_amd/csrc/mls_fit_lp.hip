@@ -43,8 +43,8 @@
 //   MFMA waves, iteration c: build the A operands (weights) from the tables
 //                            of chunk c and run its MFMAs
 // so the global-memory latency of a chunk is hidden behind a whole chunk of
-// matrix work.  With the Wendland weight the chunks walk the runs of
-// cell-sorted points that the tile's support can reach (mls_cells.hip).
+// matrix work.  With the Wendland weight the chunks walk the tile's list of
+// cell-sorted points within reach of its nodes (mls_cells.hip).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -112,80 +112,31 @@ struct LPParams {
   float* fields;
   uint8_t* deg_out;
   float* grads;           // [D][2][H][W] or null
-  const uint32_t* cell_start;
-  const uint32_t* torder;
-  int ncx, ncy;
-  CellGeom geom;
+  const uint32_t* torder;      // node tiles by descending work (Wendland)
+  const uint32_t* tile_start;  // per-tile point lists (Wendland): [tiles + 1]
+  const uint32_t* tile_list;   //   cell-ordered point indices, or null
 };
 
-// A chunk: points [k, k + kn).  Chunks never straddle two cell rows.
+// A chunk: entries [k, k + kn) of the tile's point sequence (all points,
+// or the tile's point list with a compactly supported weight).
 struct Chunk {
   int64_t k;
   int kn;
   bool valid;
 };
 
-// Walks the chunks of a tile: all points (dense), or the runs of cells in
-// rows cy0..cy1, columns cx0..cx1 (each run contiguous in cell order).
 struct Walker {
   int64_t k, kend;
-  int cy, cy1, cx0, cx1;
-  bool done;
 };
 
-template <bool CELLS>
-__device__ __forceinline__ void walker_row(const LPParams& p, Walker& w) {
-  while (w.cy <= w.cy1) {
-    const int64_t a = p.cell_start[w.cy * p.ncx + w.cx0];
-    const int64_t b = p.cell_start[w.cy * p.ncx + w.cx1 + 1];
-    if (b > a) {
-      w.k = a;
-      w.kend = b;
-      return;
-    }
-    ++w.cy;
-  }
-  w.done = true;
-}
-
-template <bool CELLS>
-__device__ __forceinline__ Walker walker_begin(const LPParams& p, int cx0, int cx1, int cy0,
-                                               int cy1) {
-  Walker w;
-  w.done = false;
-  w.cx0 = cx0;
-  w.cx1 = cx1;
-  if (!CELLS) {
-    w.k = 0;
-    w.kend = p.n;
-    w.cy = w.cy1 = 0;
-    return w;
-  }
-  w.cy = cy0;
-  w.cy1 = cy1;
-  walker_row<CELLS>(p, w);
-  return w;
-}
-
 // Take the next chunk (invalid once the walk is over).
-template <bool CELLS>
-__device__ __forceinline__ Chunk walker_take(const LPParams& p, Walker& w) {
+__device__ __forceinline__ Chunk walker_take(Walker& w) {
   Chunk c;
-  c.valid = !w.done;
+  c.valid = w.k < w.kend;
   c.k = w.k;
-  c.kn = 0;
-  if (w.done) return c;
   const int64_t left = w.kend - w.k;
-  c.kn = left < KT ? (int)left : KT;
+  c.kn = !c.valid ? 0 : (left < KT ? (int)left : KT);
   w.k += c.kn;
-  if (w.k >= w.kend) {
-    if (!CELLS) {
-      w.done = true;
-    } else {
-      ++w.cy;
-      walker_row<CELLS>(p, w);
-    }
-  }
   return c;
 }
 
@@ -241,7 +192,7 @@ __device__ __forceinline__ void raw_load(const LPParams& p, const Chunk& ch, int
     if (ch.valid && e < (2 + Ds) * KT) {
       const int row = e / KT, k = e - row * KT;
       if (k < ch.kn) {
-        const int64_t gi = ch.k + k;
+        const int64_t gi = p.tile_list ? (int64_t)p.tile_list[ch.k + k] : ch.k + k;
         if (row == 0) v = p.pts[2 * gi];
         else if (row == 1) v = p.pts[2 * gi + 1];
         else v = p.vals_t[(int64_t)(d0 + row - 2) * p.n + gi];
@@ -381,19 +332,17 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   // tile anchor (rounded to float32; node offsets are taken in this frame)
   const float cxr = (float)(p.x0 + (double)(c0 + kCols / 2) * p.dx);
   const float cyr = (float)(p.y0 + (double)(r0 + kRows / 2) * p.dy);
-  int cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
-  if (CELLS)
-    tile_cell_range(p.geom, tile % p.tiles_x, tile / p.tiles_x, p.ncx, p.ncy, &cx0, &cx1, &cy0,
-                    &cy1);
 
   // double buffers, selected by chunk parity b
   auto feat = [&](int b) { return (T*)(lds_lp + L::kFeat0 + b * L::kFeatB); };
   auto tab = [&](int b) { return (float*)(lds_lp + L::kTab0 + b * L::kTabB); };
   auto raw = [&](int b) { return (float*)(lds_lp + L::kRaw0 + b * L::kRawB); };
 
-  Walker wk = walker_begin<CELLS>(p, cx0, cx1, cy0, cy1);
-  Chunk ch0 = walker_take<CELLS>(p, wk);
-  Chunk ch1 = walker_take<CELLS>(p, wk);
+  Walker wk;
+  wk.k = CELLS ? (int64_t)p.tile_start[tile] : 0;
+  wk.kend = CELLS ? (int64_t)p.tile_start[tile + 1] : p.n;
+  Chunk ch0 = walker_take(wk);
+  Chunk ch1 = walker_take(wk);
 
   // feature rows past this slab's F are never written: zero them once in
   // both buffers
@@ -432,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   const int k8 = (lane >> 4) * 8;   // this lane's 8 points of a 32-point k-step
   int c = 0;
   while (ch0.valid) {
-    const Chunk ch2 = walker_take<CELLS>(p, wk);
+    const Chunk ch2 = walker_take(wk);
     if (mma) {
       const float* gx = tab(c & 1);
       const float* gy = tab(c & 1) + kCols * KSF;
@@ -660,20 +609,17 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
   p.fields = a.fields;
   p.deg_out = a.deg_out;
   p.grads = a.grads;
-  p.cell_start = nullptr;
   p.torder = nullptr;
-  p.ncx = p.ncy = 0;
-  p.geom = CellGeom{0, 0, 1, a.x0, a.y0, a.dx, a.dy, a.h};
+  p.tile_start = nullptr;
+  p.tile_list = nullptr;
   const bool wend = a.wkind == 1;
   if (wend) {
     if (!cells) return hipErrorInvalidValue;
     p.pts = cells->pts_s;
     p.vals_t = cells->vals_ts;
-    p.cell_start = cells->cell_start;
     p.torder = cells->torder;
-    p.ncx = cells->ncx;
-    p.ncy = cells->ncy;
-    p.geom = cells->geom;
+    p.tile_start = cells->tile_start;
+    p.tile_list = cells->tile_list;
     return fp16 ? launch_lp_terms<_Float16, true>(p, a.degree, nts, terms, stream)
                 : launch_lp_terms<__bf16, true>(p, a.degree, nts, terms, stream);
   }

@@ -106,6 +106,12 @@ struct CellArgs {
   float* pts_s;            // [n][2] in cell order
   float* vals_ts;          // [D][n] in cell order
   uint32_t* torder;        // [tiles] node tiles by descending work
+  // per-tile point lists: the cell-ordered indices of the points within h
+  // of some node of the tile (in cell order), tile t's entries at
+  // [tile_start[t], tile_start[t + 1]) of tile_list
+  uint32_t* tile_start;    // [tiles + 1]
+  uint32_t* tile_list;     // [list_cap]
+  int64_t list_cap;
   // scratch
   uint32_t* keys;          // [n]
   uint32_t* keys2;         // [n]
@@ -144,6 +150,8 @@ struct FitPlan {
   size_t o_pmin, o_pmax, o_shift, o_scale, o_vals;
   size_t o_keys, o_keys2, o_perm, o_perm2, o_hist, o_cs, o_pts, o_vals_s;
   size_t o_tk, o_tk2, o_to, o_to2, o_th;
+  size_t o_ts, o_tl;
+  int64_t list_cap;       // entries of the per-tile point lists, at most
   size_t total;
   int ncx, ncy, tiles_x, tiles;
   CellGeom geom;
@@ -158,9 +166,15 @@ struct LPCells {
   const float* vals_ts;
   const uint32_t* cell_start;
   const uint32_t* torder;
+  const uint32_t* tile_start;
+  const uint32_t* tile_list;
   int ncx, ncy;
   CellGeom geom;
 };
+
+// Upper bound of the per-tile point list entries: a point lies within h of
+// the node rectangles of at most this many tiles.
+int64_t tile_list_bound(int64_t n, double h, double dx, double dy, int tiles_x, int tiles_y);
 
 // Marching squares over D fields at n_iso isovalues each.
 struct ContourArgs {

@@ -44,6 +44,14 @@ def compare(gpu_fields, gpu_deg, or_fields, or_deg, or_dmin, values, dmin_pass=1
                       "max": float(err[:, sel].max()) if sel.any() else 0.0,
                       "rms": float(np.sqrt(np.mean(err[:, sel] ** 2))) if sel.any() else 0.0}
     out["bins"] = bins
+    # the conditioning-scaled error err * d_min^2 over same-degree nodes with
+    # 1e-3 <= d_min < 1e-2 (where the amplified float32 sums dominate every
+    # other error source), and the largest oracle d_min among degree
+    # mismatches
+    sel = both & (dm >= 1e-3) & (dm < 1e-2)
+    out["max_err_dmin2"] = float((err[:, sel] * dm[sel] ** 2).max()) if sel.any() else 0.0
+    mis = (gd != od) & (od != 255) & (gd != 255)
+    out["mismatch_dmin_max"] = float(dm[mis].max()) if mis.any() else 0.0
     # NaN exactly where undetermined
     und = gd == 255
     out["nan_ok"] = bool(np.all(np.isnan(gf[:, und])) and np.all(np.isfinite(gf[:, ~und])))
