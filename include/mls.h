@@ -125,6 +125,14 @@ typedef struct {
                            slab, 0 = the library's plan, else 1 ..
                            MLS_LP_MAX_SLAB_<basis>.  A tuning knob only:
                            results are bitwise the same for every value */
+  int32_t lp_form;      /* MLS_PREC_BF16 with the Gaussian weight, linear or
+                           quadratic basis, no gradients: 0 = the library's
+                           choice, 1 = one pass (moments and right-hand
+                           sides together, F = n_mom + m D columns),
+                           2 = two passes (shape-function form: the moments
+                           and each node's ladder first, then the effective
+                           weights w (y^T b) against the attributes, F =
+                           n_mom + D columns).  Ignored elsewhere */
 } mls_solve_opts;
 
 typedef struct mls_context mls_context;
@@ -251,6 +259,37 @@ mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* 
                       const int32_t* d_adj, int64_t n_adj, const int32_t* d_fan_start,
                       const int32_t* d_fan, int64_t n_fan, const mls_layout_params* params,
                       int32_t iterations, void* stream);
+
+/*
+ * Per-stage timing of a context's calls (the paper reports per-stage times,
+ * Table 1).  With tracing on, every mls_fit, mls_fit_grad, mls_contour and
+ * mls_layout call records timing events on its stream around its stages:
+ *   fit:     "stage" (16-bit staging), "cells" (compact-support cell list
+ *            and tile lists), "contract" (the weight x feature contraction
+ *            and the per-node solve), "hits" (inverse-distance exact hits)
+ *   contour: "passes";  layout: "iterations"
+ * Recording adds events only; nothing waits for them until a record is read
+ * back.  When jsonl_path is given (may be NULL), each call appends one JSON
+ * line {"call", the request's sizes, "stages_ms": {...}, "total_ms"} to it
+ * once its events complete (read back lazily, at most 64 calls pending).
+ * Turning tracing off (or on again) first reads back every pending call.
+ */
+#define MLS_TRACE_MAX_STAGES 4
+typedef struct {
+  char call[16];                     /* "fit", "fit_grad", "contour", "layout" */
+  int32_t form;                      /* fits: 0 float64 contraction, 1 16-bit one
+                                        pass, 2 16-bit two passes; -1 otherwise */
+  int32_t n_stages;
+  char stage[MLS_TRACE_MAX_STAGES][16];
+  double ms[MLS_TRACE_MAX_STAGES];   /* per stage, in stream order */
+  double total_ms;
+} mls_trace_record;
+
+mls_status mls_context_trace(mls_context* ctx, int32_t enable, const char* jsonl_path);
+
+/* Wait for the context's traced calls and return the last one's stage
+ * times.  MLS_ERR_INVALID_ARG if no call has been traced. */
+mls_status mls_context_trace_last(mls_context* ctx, mls_trace_record* out);
 
 /*
  * Device scratch bytes mls_fit needs for this request (0 for MLS_PREC_F64);

@@ -21,7 +21,7 @@ EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
            "mls_server_poll", "mls_server_wait", "mls_server_last_error",
            "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad", "mls_layout",
-           "mls_contour_static")
+           "mls_contour_static", "mls_context_trace", "mls_context_trace_last")
 
 
 class MlsGrid(ctypes.Structure):
@@ -37,7 +37,8 @@ class MlsWeight(ctypes.Structure):
 
 class MlsSolveOpts(ctypes.Structure):
     _fields_ = [("pivot_tol", ctypes.c_double), ("weight_floor", ctypes.c_double),
-                ("lp_terms", ctypes.c_int32), ("lp_slab", ctypes.c_int32)]
+                ("lp_terms", ctypes.c_int32), ("lp_slab", ctypes.c_int32),
+                ("lp_form", ctypes.c_int32)]
 
 
 class MlsLayoutParams(ctypes.Structure):
@@ -56,6 +57,16 @@ class MlsResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_end", ctypes.c_double), ("detail", ctypes.c_char * 128)]
+
+
+TRACE_MAX_STAGES = 4   # MLS_TRACE_MAX_STAGES
+
+
+class MlsTraceRecord(ctypes.Structure):
+    _fields_ = [("call", ctypes.c_char * 16), ("form", ctypes.c_int32),
+                ("n_stages", ctypes.c_int32),
+                ("stage", (ctypes.c_char * 16) * TRACE_MAX_STAGES),
+                ("ms", ctypes.c_double * TRACE_MAX_STAGES), ("total_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -100,6 +111,10 @@ def load():
     lib.mls_fit_scratch_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(MlsWeight),
                                           ctypes.POINTER(MlsGrid)]
     lib.mls_fit_scratch_bytes.restype = ctypes.c_size_t
+    lib.mls_context_trace.argtypes = [P, i32, ctypes.c_char_p]
+    lib.mls_context_trace.restype = ctypes.c_int
+    lib.mls_context_trace_last.argtypes = [P, ctypes.POINTER(MlsTraceRecord)]
+    lib.mls_context_trace_last.restype = ctypes.c_int
     lib.mls_context_reserve.argtypes = [P, ctypes.c_size_t]
     lib.mls_context_reserve.restype = ctypes.c_int
     lib.mls_server_create.argtypes = [i32, ctypes.c_size_t, i32, ctypes.c_size_t,

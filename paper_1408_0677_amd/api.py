@@ -47,6 +47,25 @@ class Context:
     def handle(self):
         return self._ptr
 
+    def trace(self, enable: bool = True, jsonl_path: str | None = None):
+        """Per-stage timing of this context's calls (mls_context_trace); with
+        ``jsonl_path`` one JSON line per call is appended there."""
+        _check(_lib.load().mls_context_trace(self._ptr, 1 if enable else 0,
+                                             None if jsonl_path is None
+                                             else str(jsonl_path).encode()),
+               "mls_context_trace")
+
+    def trace_last(self) -> dict:
+        """Stage times (ms) of the last traced call: {"call", "stages": {name:
+        ms}, "total_ms"}; waits for the traced calls to finish."""
+        rec = _lib.MlsTraceRecord()
+        _check(_lib.load().mls_context_trace_last(self._ptr, ctypes.byref(rec)),
+               "mls_context_trace_last")
+        stages = {bytes(rec.stage[k].value).decode(): float(rec.ms[k])
+                  for k in range(rec.n_stages)}
+        return {"call": rec.call.decode(), "form": int(rec.form), "stages": stages,
+                "total_ms": float(rec.total_ms)}
+
     def close(self):
         if self._ptr:
             _lib.load().mls_context_destroy(self._ptr)
@@ -130,7 +149,7 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
         h: float = 0.05, alpha: float = 1.0, precision: str = "f64",
         pivot_tol: float = 1e-8, weight_floor: float = 1e-6, lp_terms: int = 0, out=None,
         degree_out=None, want_degree: bool = True, ctx: Context | None = None,
-        stream=None, lp_slab: int = 0):
+        stream=None, lp_slab: int = 0, lp_form: int = 0):
     """MLS fields of ``values`` (N, D) at the nodes of ``grid``.
 
     ``points`` float32 (N, 2) and ``values`` float32 (N, D) are contiguous
@@ -153,7 +172,7 @@ def fit(points, values, grid: dict, basis: str = "linear", weight: str = "gaussi
     g = grid_struct(grid)
     wt = _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha))
     opts = _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor), int(lp_terms),
-                             int(lp_slab))
+                             int(lp_slab), int(lp_form))
     st = _lib.load().mls_fit(ctx.handle, _ptr(points), _ptr(values), n, d, BASIS[basis],
                              ctypes.byref(wt), ctypes.byref(g), PRECISION[precision],
                              ctypes.byref(opts), _ptr(out), _ptr(degree_out),
@@ -394,7 +413,7 @@ class Server:
     def submit(self, pointset: int, grid: dict, out, degree_out=None, basis: str = "linear",
                weight: str = "gaussian", h: float = 0.05, alpha: float = 1.0,
                precision: str = "f64", pivot_tol: float = 1e-8, weight_floor: float = 1e-6,
-               lp_terms: int = 0, lp_slab: int = 0) -> int:
+               lp_terms: int = 0, lp_slab: int = 0, lp_form: int = 0) -> int:
         import torch
         # point sets of this server: the outputs must fit them (an unknown
         # id is left to the library, which refuses it without a launch)
@@ -411,7 +430,7 @@ class Server:
                               _lib.MlsWeight(WEIGHT[weight], float(h), float(alpha)),
                               grid_struct(grid), PRECISION[precision],
                               _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor),
-                                                int(lp_terms), int(lp_slab)),
+                                                int(lp_terms), int(lp_slab), int(lp_form)),
                               out.data_ptr(),
                               None if degree_out is None else degree_out.data_ptr())
         t = ctypes.c_uint64()

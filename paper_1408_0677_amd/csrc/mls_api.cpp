@@ -7,7 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "../../include/mls.h"
 #include "mls_internal.h"
@@ -17,8 +20,27 @@ struct Scratch {
   size_t bytes = 0;
 };
 
+// One traced call: its stages' end events (after a start event) and what
+// the JSON line reports about the call.
+struct TraceCall {
+  std::string call;
+  int form = -1;
+  std::string meta;                 // JSON members describing the request
+  std::vector<hipEvent_t> ev;       // ev[0] start, ev[k] end of stage k
+  std::vector<std::string> stages;  // stage k's name at stages[k - 1]
+};
+
+struct Tracing {
+  bool on = false;
+  std::string path;                 // JSON-lines file, or empty
+  std::deque<TraceCall> pending;    // recorded, not yet read back
+  mls_trace_record last{};
+  bool have_last = false;
+};
+
 struct mls_context {
   int device;
+  Tracing trace;
   // device scratch, grown on demand: contour counts, offsets, tile sums
   Scratch scratch;
   // fit staging: attribute ranges, shift/scale, normalised values
@@ -115,6 +137,122 @@ mls_status scratch_release(mls_context* ctx, hipStream_t s) {
   ctx->last_stream = s;
   ctx->used = true;
   return MLS_OK;
+}
+
+// ---- tracing: per-stage hipEvent timing behind mls_context_trace ----
+
+void trace_destroy(TraceCall& c) {
+  for (hipEvent_t e : c.ev) (void)hipEventDestroy(e);
+  c.ev.clear();
+}
+
+// Wait for a traced call, turn its events into stage times, append its JSON
+// line and keep it as the context's last record.
+void trace_finalize(mls_context* ctx, TraceCall& c) {
+  mls_trace_record r{};
+  std::snprintf(r.call, sizeof(r.call), "%s", c.call.c_str());
+  r.form = c.form;
+  bool ok = !c.ev.empty() && hipEventSynchronize(c.ev.back()) == hipSuccess;
+  double total = 0.0;
+  const int ns = (int)c.stages.size() < MLS_TRACE_MAX_STAGES ? (int)c.stages.size()
+                                                             : MLS_TRACE_MAX_STAGES;
+  for (int k = 0; ok && k < ns; ++k) {
+    float ms = 0.0f;
+    ok = hipEventElapsedTime(&ms, c.ev[k], c.ev[k + 1]) == hipSuccess;
+    std::snprintf(r.stage[k], sizeof(r.stage[k]), "%s", c.stages[k].c_str());
+    r.ms[k] = ms;
+    total += ms;
+  }
+  (void)hipGetLastError();
+  trace_destroy(c);
+  if (!ok) return;
+  r.n_stages = ns;
+  r.total_ms = total;
+  ctx->trace.last = r;
+  ctx->trace.have_last = true;
+  if (ctx->trace.path.empty()) return;
+  if (FILE* f = std::fopen(ctx->trace.path.c_str(), "a")) {
+    std::fprintf(f, "{\"call\": \"%s\", \"form\": %d, %s\"stages_ms\": {", r.call, r.form,
+                 c.meta.c_str());
+    for (int k = 0; k < ns; ++k)
+      std::fprintf(f, "%s\"%s\": %.6f", k ? ", " : "", r.stage[k], r.ms[k]);
+    std::fprintf(f, "}, \"total_ms\": %.6f}\n", total);
+    std::fclose(f);
+  }
+}
+
+// Read back the pending calls whose last event has completed (all of them
+// when `all`), oldest first.
+void trace_drain(mls_context* ctx, bool all) {
+  while (!ctx->trace.pending.empty()) {
+    TraceCall& c = ctx->trace.pending.front();
+    if (!all && hipEventQuery(c.ev.back()) != hipSuccess) {
+      (void)hipGetLastError();
+      if (ctx->trace.pending.size() < 64) break;   // keep at most 64 calls in flight
+    }
+    TraceCall done = std::move(c);
+    ctx->trace.pending.pop_front();
+    trace_finalize(ctx, done);
+  }
+}
+
+// Records the stages of one call on its stream when the context traces.
+class Tracer {
+ public:
+  Tracer(mls_context* ctx, hipStream_t s, const char* call, std::string meta)
+      : ctx_(ctx), s_(s), on_(ctx->trace.on) {
+    if (!on_) return;
+    c_.call = call;
+    c_.meta = std::move(meta);
+    on_ = record();
+  }
+  ~Tracer() {
+    if (on_) trace_destroy(c_);
+  }
+  // End of a stage that began at the previous mark.
+  void mark(const char* stage) {
+    if (!on_) return;
+    c_.stages.emplace_back(stage);
+    on_ = record();
+    if (!on_) trace_destroy(c_);
+  }
+  void set_form(int form) { c_.form = form; }
+  void finish() {
+    if (!on_ || c_.stages.empty()) return;
+    ctx_->trace.pending.push_back(std::move(c_));
+    c_ = TraceCall();
+    on_ = false;
+    trace_drain(ctx_, false);
+  }
+
+ private:
+  bool record() {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    c_.ev.push_back(e);
+    if (hipEventRecord(e, s_) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  }
+  mls_context* ctx_;
+  hipStream_t s_;
+  bool on_;
+  TraceCall c_;
+};
+
+std::string fit_meta(int64_t n, int32_t d, int32_t basis, int32_t wkind, const mls_grid* g,
+                     int32_t precision) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf),
+                "\"n\": %lld, \"d\": %d, \"basis\": %d, \"weight\": %d, \"width\": %d, "
+                "\"height\": %d, \"precision\": %d, ",
+                (long long)n, d, basis, wkind, g->width, g->height, precision);
+  return buf;
 }
 
 }  // namespace
@@ -259,6 +397,7 @@ mls_status mls_context_create(int32_t device, mls_context** out) {
 void mls_context_destroy(mls_context* ctx) {
   if (!ctx) return;
   if (hipSetDevice(ctx->device) == hipSuccess) {
+    for (TraceCall& c : ctx->trace.pending) trace_destroy(c);
     if (ctx->scratch.ptr) (void)hipFree(ctx->scratch.ptr);
     if (ctx->fit_scratch.ptr) (void)hipFree(ctx->fit_scratch.ptr);
 
@@ -305,7 +444,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
     return fail(MLS_ERR_INVALID_ARG, "grid origin and spacing must be finite");
   double tau = 1e-8, floor_w = 1e-6;
   int terms = precision == MLS_PREC_FP16 ? 2 : 3;
-  int slab = 0;
+  int slab = 0, form = 0;
   if (opts) {
     tau = opts->pivot_tol;
     floor_w = opts->weight_floor;
@@ -319,6 +458,9 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       return fail(MLS_ERR_INVALID_ARG, "lp_slab = %d; need 0..%d for this basis", opts->lp_slab,
                   max_slab);
     slab = opts->lp_slab;
+    if (opts->lp_form < 0 || opts->lp_form > 2)
+      return fail(MLS_ERR_INVALID_ARG, "lp_form = %d; need 0..2", opts->lp_form);
+    form = opts->lp_form;
     if (!is_finite(tau) || !(tau > 0.0) || !(tau <= 1.0))
       return fail(MLS_ERR_INVALID_ARG, "pivot_tol = %g; need 0 < tau <= 1", tau);
     if (!is_finite(floor_w) || floor_w < 0.0)
@@ -369,10 +511,13 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   a.tau = tau;
   a.floor_w = floor_w;
   a.lp_slab = slab;
+  a.lp_form = form;
   a.fields = d_fields;
   a.deg_out = d_degree;
   a.grads = d_grad;
   hipStream_t s = (hipStream_t)stream;
+  Tracer tr(ctx, s, d_grad ? "fit_grad" : "fit",
+            fit_meta(n, d, basis, weight->kind, grid, precision));
   if (precision == MLS_PREC_F64) {
     mls::FitPlan plan{};
     if (weight->kind == MLS_W_INVPOW) {
@@ -383,6 +528,8 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
     }
     e = mls::launch_fit_f64(a, s);
     if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+    tr.set_form(0);
+    tr.mark("contract");
     if (weight->kind == MLS_W_INVPOW) {
       char* base = (char*)ctx->fit_scratch.ptr;
       mls::HitArgs hta;
@@ -406,8 +553,11 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       hta.hist = (uint32_t*)(base + plan.o_hist);
       e = mls::launch_hits(hta, s);
       if (e != hipSuccess) return device_fail(e, "exact-hit pass launch");
+      tr.mark("hits");
+      tr.finish();
       return scratch_release(ctx, s);
     }
+    tr.finish();
     return MLS_OK;
   }
   const bool fp16 = precision == MLS_PREC_FP16;
@@ -450,9 +600,14 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   float* vals_t = (float*)(base + plan.o_vals);
   e = mls::launch_stage(d_values, n, d, pmin, pmax, shift, scale, vals_t, s);
   if (e != hipSuccess) return device_fail(e, "staging kernel launch");
+  tr.mark("stage");
+  tr.set_form(mls::lp_use_shape_form(a.degree, d, fp16, weight->kind, d_grad != nullptr, terms,
+                                     0, form) ? 2 : 1);
   if (weight->kind != MLS_W_WENDLAND_C2) {
     e = mls::launch_fit_lp(a, vals_t, shift, scale, fp16, terms, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+    tr.mark("contract");
+    tr.finish();
     return scratch_release(ctx, s);
   }
   mls::CellArgs ca;
@@ -483,6 +638,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   ca.list_cap = plan.list_cap;
   e = mls::launch_cells(ca, s);
   if (e != hipSuccess) return device_fail(e, "cell list kernels");
+  tr.mark("cells");
   mls::LPCells cl;
   cl.pts_s = ca.pts_s;
   cl.vals_ts = ca.vals_ts;
@@ -495,6 +651,8 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   cl.geom = plan.geom;
   e = mls::launch_fit_lp(a, vals_t, shift, scale, fp16, terms, &cl, s);
   if (e != hipSuccess) return device_fail(e, "fit kernel launch");
+  tr.mark("contract");
+  tr.finish();
   return scratch_release(ctx, s);
 }
 
@@ -548,9 +706,43 @@ mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* 
   a.iterations = iterations;
   a.buf0 = (double*)ctx->fit_scratch.ptr;
   a.buf1 = (double*)((char*)ctx->fit_scratch.ptr + half);
+  char meta[96];
+  std::snprintf(meta, sizeof(meta), "\"n\": %lld, \"iterations\": %d, ", (long long)n,
+                iterations);
+  Tracer tr(ctx, s, "layout", meta);
   e = mls::launch_layout(a, s);
   if (e != hipSuccess) return device_fail(e, "layout kernel launch");
+  tr.mark("iterations");
+  tr.finish();
   return scratch_release(ctx, s);
+}
+
+mls_status mls_context_trace(mls_context* ctx, int32_t enable, const char* jsonl_path) {
+  g_last_error[0] = '\0';
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+  if (enable != 0 && enable != 1) return fail(MLS_ERR_INVALID_ARG, "enable = %d", enable);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  trace_drain(ctx, true);
+  if (jsonl_path && jsonl_path[0]) {
+    FILE* f = std::fopen(jsonl_path, "a");
+    if (!f) return fail(MLS_ERR_INVALID_ARG, "cannot open %s for appending", jsonl_path);
+    std::fclose(f);
+  }
+  ctx->trace.on = enable == 1;
+  ctx->trace.path = jsonl_path ? jsonl_path : "";
+  return MLS_OK;
+}
+
+mls_status mls_context_trace_last(mls_context* ctx, mls_trace_record* out) {
+  g_last_error[0] = '\0';
+  if (!ctx || !out) return fail(MLS_ERR_INVALID_ARG, "ctx or out is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  trace_drain(ctx, true);
+  if (!ctx->trace.have_last) return fail(MLS_ERR_INVALID_ARG, "no traced call on this context");
+  *out = ctx->trace.last;
+  return MLS_OK;
 }
 
 mls_status mls_context_reserve(mls_context* ctx, size_t bytes) {
@@ -695,8 +887,14 @@ mls_status mls_contour(mls_context* ctx, const float* d_fields, int32_t d,
                                           nullptr);
   hipStream_t s = (hipStream_t)stream;
   if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
+  char meta[160];
+  std::snprintf(meta, sizeof(meta), "\"d\": %d, \"n_iso\": %d, \"width\": %d, "
+                "\"height\": %d, ", d, n_iso, grid->width, grid->height);
+  Tracer tr(ctx, s, "contour", meta);
   e = mls::launch_contour(a, s);
   if (e != hipSuccess) return device_fail(e, "contour kernel launch");
+  tr.mark("passes");
+  tr.finish();
   if ((st = scratch_release(ctx, s)) != MLS_OK) return st;
   e = hipMemcpyAsync(ctx->pinned, a.total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return device_fail(e, "count read-back");

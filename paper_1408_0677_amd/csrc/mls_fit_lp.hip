@@ -470,6 +470,471 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-pass (shape-function) form of the same fit, for the bfloat16 path with
+// the Gaussian weight.  The field at node p is
+//   field_d(p) = y_p^T R_t,d = sum_i w_ip (y_p^T b_t(u_i)) f_i,d,
+// y_p = T'^T M_p'^{-1} e_0 the tile-frame coefficients of the node's shape
+// function (mls_solve.h).  Pass 1 contracts the weights with the moment
+// monomials only (one 16-column feature tile, S1 terms, split weight) and
+// solves every node's ladder for y_p; pass 2 streams the points again and
+// contracts the effective weights w_ip (y_p^T b_t(u_i)), formed per pair in
+// float32 and split hi + lo, with the attributes (two bfloat16 terms each).
+// The contraction width falls from n_mom + m D to n_mom + D (399 -> 79 for
+// the quadratic basis with 64 attributes); the solve runs once per node and
+// attribute slab instead of per feature.  The error stays the float32
+// accumulation of the moments in pass 1: the effective weights and the
+// attribute terms add about 2^-16 relative per pair, which is not amplified
+// by the conditioning (a numpy model of both forms gives the same error).
+// ---------------------------------------------------------------------------
+
+constexpr int kShapeDsCap = 64;    // attributes per workgroup slab
+constexpr int kShapeS2 = 2;        // bfloat16 terms per attribute value
+
+template <int DEG, int NTV, int S1>
+struct ShapeLayout {
+  static constexpr int m = DEG == 1 ? 3 : 6;
+  static constexpr int nmom = DEG == 1 ? 6 : 15;
+  static constexpr int kRows1 = S1 * 16;                 // pass 1 feature rows
+  static constexpr int kRows2 = kShapeS2 * NTV * 16;     // pass 2 feature rows
+  static constexpr int kFeatRows = kRows1 > kRows2 ? kRows1 : kRows2;
+  static constexpr int kDs = NTV * 16;
+  static constexpr int kRawFloats = (2 + kDs) * KT;
+  static constexpr int kRawIt = (kRawFloats + kProd - 1) / kProd;
+  static constexpr int kFeatB = kFeatRows * KSH * 2;
+  static constexpr int kTabB = (kCols + kRows) * KSF * 4;
+  static constexpr int kBasB = m * KSF * 4;
+  static constexpr int kRawB = kRawFloats * 4;
+  static constexpr int kFeat0 = 0;
+  static constexpr int kTab0 = kFeat0 + 2 * kFeatB;
+  static constexpr int kBas0 = kTab0 + 2 * kTabB;
+  static constexpr int kRaw0 = kBas0 + 2 * kBasB;
+  static constexpr int kLoop = kRaw0 + 2 * kRawB;
+  static constexpr int kEpiStride = 16 + 1;
+  static constexpr int kEpi = kMmaWaves * 16 * R * kEpiStride * 4;
+  static constexpr int kMain = kLoop > kEpi ? kLoop : kEpi;
+  // per node: the shape coefficients y (float32) and the degree code
+  static constexpr int kY0 = kMain;
+  static constexpr int kCode0 = kY0 + kRows * kCols * m * 4;
+  static constexpr int kBytes = kCode0 + kRows * kCols;
+  static_assert(kBytes <= 160 * 1024, "LDS budget");
+};
+
+// Producer: global -> registers for one raw chunk of `nv` attributes.
+template <int RAWIT>
+__device__ __forceinline__ void shape_raw_load(const LPParams& p, const Chunk& ch, int d0, int nv,
+                                               int pt, float (&r)[RAWIT]) {
+#pragma unroll
+  for (int it = 0; it < RAWIT; ++it) {
+    const int e = pt + it * kProd;
+    float v = 0.0f;
+    if (ch.valid && e < (2 + nv) * KT) {
+      const int row = e / KT, k = e - row * KT;
+      if (k < ch.kn) {
+        const int64_t gi = ch.k + k;
+        if (row == 0) v = p.pts[2 * gi];
+        else if (row == 1) v = p.pts[2 * gi + 1];
+        else v = p.vals_t[(int64_t)(d0 + row - 2) * p.n + gi];
+      }
+    }
+    r[it] = v;
+  }
+}
+
+template <int RAWIT>
+__device__ __forceinline__ void shape_raw_store(float* raw, int nv, int pt,
+                                                const float (&r)[RAWIT]) {
+#pragma unroll
+  for (int it = 0; it < RAWIT; ++it) {
+    const int e = pt + it * kProd;
+    if (e < (2 + nv) * KT) raw[e] = r[it];
+  }
+}
+
+// Producer: the separable Gaussian tables of a chunk (32 rows: 16 node
+// columns, then 16 node rows, x 64 points; zero past the chunk).
+__device__ __forceinline__ void gauss_tables(const LPParams& p, const float* raw, int kn,
+                                             float* tab, int pt, const float (&toff)[kTabIt],
+                                             float cxr, float cyr) {
+#pragma unroll
+  for (int it = 0; it < kTabIt; ++it) {
+    const int e = pt + it * kProd;
+    const int k = e & (KT - 1), row = e / KT;
+    float v = 0.0f;
+    if (k < kn) {
+      const float u = (row < kCols ? raw[k] - cxr : raw[KT + k] - cyr) * p.inv_h - toff[it];
+      v = __expf(-u * u);
+    }
+    tab[row * KSF + k] = v;
+  }
+}
+
+// Split two float32 values into `S` bfloat16 terms each (each term the
+// rounding of what the earlier ones left), written as pairs at rows
+// dst + s * stride.
+template <int S>
+__device__ __forceinline__ void emit_terms(__bf16* dst, size_t stride, float v0, float v1) {
+  typedef __bf16 B2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const __bf16 t0 = (__bf16)v0, t1 = (__bf16)v1;
+    v0 -= (float)t0;
+    v1 -= (float)t1;
+    B2 pr;
+    pr.x = t0;
+    pr.y = t1;
+    *(B2*)(dst + (size_t)s * stride) = pr;
+  }
+}
+
+// Monomials u_x^a u_y^b (a + b <= 2 DEG) of a point in the tile frame, in
+// mono_index order; zero for points beyond the reach of every node.
+template <int DEG>
+__device__ __forceinline__ void point_monomials(const LPParams& p, float x, float y, float cxr,
+                                                float cyr, float (&mo)[DEG == 1 ? 6 : 15]) {
+  const float ux = (x - cxr) * p.inv_h;
+  const float uy = (y - cyr) * p.inv_h;
+  const float one = (ux * ux + uy * uy <= p.cutoff2) ? 1.0f : 0.0f;
+  mo[0] = one;
+  mo[1] = one * ux;
+  mo[2] = one * uy;
+  mo[3] = mo[1] * ux;
+  mo[4] = mo[1] * uy;
+  mo[5] = mo[2] * uy;
+  if (DEG == 2) {
+    mo[6] = mo[3] * ux;
+    mo[7] = mo[3] * uy;
+    mo[8] = mo[4] * uy;
+    mo[9] = mo[5] * uy;
+    mo[10] = mo[6] * ux;
+    mo[11] = mo[6] * uy;
+    mo[12] = mo[7] * uy;
+    mo[13] = mo[8] * uy;
+    mo[14] = mo[9] * uy;
+  }
+}
+
+// Producer, pass 1: tables and the moment monomials (S1 terms, rows
+// s * 16 + j).  Pass 2: tables, the basis rows b_j of the chunk's points
+// (float32, row j of `bas`), and the attribute terms (rows s * kDs + d).
+// A thread owns two consecutive points and one eighth of the rows.
+template <int DEG, int NTV, int S1, bool PASS2>
+__device__ __forceinline__ void shape_chunk(const LPParams& p, const float* raw, int kn, int nv,
+                                            float* tab, float* bas, __bf16* G, int pt,
+                                            const float (&toff)[kTabIt], float cxr,
+                                            float cyr) {
+  using L = ShapeLayout<DEG, NTV, S1>;
+  gauss_tables(p, raw, kn, tab, pt, toff, cxr, cyr);
+  const int pp = pt & 31, g = pt >> 5;
+  const int k0 = 2 * pp;
+  float mo0[L::nmom], mo1[L::nmom];
+  point_monomials<DEG>(p, raw[k0], raw[KT + k0], cxr, cyr, mo0);
+  point_monomials<DEG>(p, raw[k0 + 1], raw[KT + k0 + 1], cxr, cyr, mo1);
+  if (!PASS2) {
+#pragma unroll
+    for (int j = 0; j < L::nmom; ++j)
+      if ((j & 7) == g) emit_terms<S1>(G + (size_t)j * KSH + k0, (size_t)16 * KSH, mo0[j], mo1[j]);
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < L::m; ++j)
+    if ((j & 7) == g) {
+      bas[j * KSF + k0] = mo0[j];
+      bas[j * KSF + k0 + 1] = mo1[j];
+    }
+  const float* rv = raw + 2 * KT;
+  for (int d = g; d < nv; d += 8)
+    emit_terms<kShapeS2>(G + (size_t)d * KSH + k0, (size_t)L::kDs * KSH, rv[d * KT + k0],
+                         rv[d * KT + k0 + 1]);
+}
+
+template <int DEG, int NTV, int S1>
+__global__ __launch_bounds__(kThreads) void fit_shape_kernel(LPParams p) {
+  using L = ShapeLayout<DEG, NTV, S1>;
+  constexpr int m = L::m;
+  extern __shared__ __attribute__((aligned(16))) char lds_sh[];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool mma = wave < kMmaWaves;
+  const int pt = tid - kMmaWaves * 64;
+  const int slab = blockIdx.x / p.tiles;
+  const int tile = (int)(blockIdx.x % p.tiles);
+  const int c0 = (tile % p.tiles_x) * kCols;
+  const int r0 = (tile / p.tiles_x) * kRows;
+  const int d0 = slab * p.Ds;
+  const int nv = min(p.Ds, p.D - d0);
+  const float cxr = (float)(p.x0 + (double)(c0 + kCols / 2) * p.dx);
+  const float cyr = (float)(p.y0 + (double)(r0 + kRows / 2) * p.dy);
+
+  auto feat = [&](int b) { return (__bf16*)(lds_sh + L::kFeat0 + b * L::kFeatB); };
+  auto tab = [&](int b) { return (float*)(lds_sh + L::kTab0 + b * L::kTabB); };
+  auto bas = [&](int b) { return (float*)(lds_sh + L::kBas0 + b * L::kBasB); };
+  auto raw = [&](int b) { return (float*)(lds_sh + L::kRaw0 + b * L::kRawB); };
+  float* ybuf = (float*)(lds_sh + L::kY0);
+  uint8_t* codes = (uint8_t*)(lds_sh + L::kCode0);
+
+  float toff[kTabIt];
+  if (!mma) table_offsets(p, pt, c0, r0, cxr, cyr, toff);
+  const int i = lane & 15;
+  const int k8 = (lane >> 4) * 8;
+  const int64_t plane = (int64_t)p.W * p.H;
+
+  // ---- pass 1: moments, then the ladder and the shape coefficients ----
+  {
+    // feature rows past the moments are never written: zero them once
+    for (int b = 0; b < 2; ++b)
+      for (int s = 0; s < S1; ++s) {
+        __bf16* z = feat(b) + ((size_t)s * 16 + L::nmom) * KSH;
+        for (int e = tid; e < (16 - L::nmom) * KSH; e += kThreads) z[e] = (__bf16)0.0f;
+      }
+    Walker wk{0, p.n};
+    Chunk ch0 = walker_take(wk);
+    Chunk ch1 = walker_take(wk);
+    float rr[L::kRawIt];
+    if (!mma) {
+      shape_raw_load<L::kRawIt>(p, ch0, d0, 0, pt, rr);
+      shape_raw_store<L::kRawIt>(raw(0), 0, pt, rr);
+      shape_raw_load<L::kRawIt>(p, ch1, d0, 0, pt, rr);
+      shape_raw_store<L::kRawIt>(raw(1), 0, pt, rr);
+    }
+    __syncthreads();
+    if (!mma && ch0.valid)
+      shape_chunk<DEG, NTV, S1, false>(p, raw(0), ch0.kn, 0, tab(0), bas(0), feat(0), pt, toff,
+                                       cxr, cyr);
+    __syncthreads();
+    floatx4 acc[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    while (ch0.valid) {
+      const Chunk ch2 = walker_take(wk);
+      if (mma) {
+        const float* gx = tab(c & 1);
+        const float* gy = tab(c & 1) + kCols * KSF;
+        const __bf16* G = feat(c & 1);
+#pragma unroll
+        for (int ks = 0; ks < KT; ks += 32) {
+          float wx[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) wx[q] = gx[i * KSF + ks + k8 + q];
+          bf16x8 ahi[R], alo[R];
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            const float* gyr = gy + (wave * R + t) * KSF + ks + k8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const float w = wx[q] * gyr[q];
+              const __bf16 hw = (__bf16)w;
+              ahi[t][q] = hw;
+              alo[t][q] = (__bf16)(w - (float)hw);
+            }
+          }
+#pragma unroll
+          for (int s = 0; s < S1; ++s) {
+            const bf16x8 b = *(const bf16x8*)(G + ((size_t)s * 16 + i) * KSH + ks + k8);
+#pragma unroll
+            for (int t = 0; t < R; ++t) acc[t] = mfma16(ahi[t], b, acc[t]);
+            if (s + 1 < S1) {
+#pragma unroll
+              for (int t = 0; t < R; ++t) acc[t] = mfma16(alo[t], b, acc[t]);
+            }
+          }
+        }
+      } else {
+        shape_raw_load<L::kRawIt>(p, ch2, d0, 0, pt, rr);
+        if (ch1.valid)
+          shape_chunk<DEG, NTV, S1, false>(p, raw((c + 1) & 1), ch1.kn, 0, tab((c + 1) & 1),
+                                           bas((c + 1) & 1), feat((c + 1) & 1), pt, toff, cxr,
+                                           cyr);
+        shape_raw_store<L::kRawIt>(raw(c & 1), 0, pt, rr);
+      }
+      __syncthreads();
+      ch0 = ch1;
+      ch1 = ch2;
+      ++c;
+    }
+    // moments -> LDS [wave][node][monomial], then one node per lane: the
+    // ladder, the degree code and y (float32)
+    float* epi = (float*)lds_sh;
+    if (mma) {
+      float* e = epi + wave * 16 * R * L::kEpiStride;
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          e[(t * 16 + 4 * (lane >> 4) + r) * L::kEpiStride + (lane & 15)] = acc[t][r];
+    }
+    __syncthreads();
+    if (mma) {
+      const float* e = epi + wave * 16 * R * L::kEpiStride;
+      for (int node = lane; node < 16 * R; node += 64) {
+        const int t = node / 16, col = node % 16;
+        const int row = wave * R + t;
+        const double ex = node_offset_xd(p, c0, col, cxr);
+        const double ey = node_offset_yd(p, r0, row, cyr);
+        Ladder<DEG> lad;
+        const int code = ladder_solve<DEG>(e + node * L::kEpiStride, ex, ey, p.tau, p.floor_w,
+                                           1.0, lad);
+        float* yv = ybuf + (row * kCols + col) * m;
+#pragma unroll
+        for (int j = 0; j < m; ++j) yv[j] = code == 255 ? 0.0f : (float)lad.y[j];
+        codes[row * kCols + col] = (uint8_t)code;
+        const int rr2 = r0 + row, cc = c0 + col;
+        if (p.deg_out && slab == 0 && rr2 < p.H && cc < p.W)
+          p.deg_out[(int64_t)rr2 * p.W + cc] = (uint8_t)code;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- pass 2: effective weights x attribute terms ----
+  {
+    // attribute rows past this slab's values are never written: zero them
+    for (int b = 0; b < 2; ++b)
+      for (int s = 0; s < kShapeS2; ++s) {
+        __bf16* z = feat(b) + ((size_t)s * L::kDs + nv) * KSH;
+        for (int e = tid; e < (L::kDs - nv) * KSH; e += kThreads) z[e] = (__bf16)0.0f;
+      }
+    // the shape coefficients of this lane's nodes (column i of its strips)
+    float yv[R][m];
+    if (mma) {
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int j = 0; j < m; ++j) yv[t][j] = ybuf[((wave * R + t) * kCols + i) * m + j];
+    }
+    Walker wk{0, p.n};
+    Chunk ch0 = walker_take(wk);
+    Chunk ch1 = walker_take(wk);
+    float rr[L::kRawIt];
+    if (!mma) {
+      shape_raw_load<L::kRawIt>(p, ch0, d0, nv, pt, rr);
+      shape_raw_store<L::kRawIt>(raw(0), nv, pt, rr);
+      shape_raw_load<L::kRawIt>(p, ch1, d0, nv, pt, rr);
+      shape_raw_store<L::kRawIt>(raw(1), nv, pt, rr);
+    }
+    __syncthreads();
+    if (!mma && ch0.valid)
+      shape_chunk<DEG, NTV, S1, true>(p, raw(0), ch0.kn, nv, tab(0), bas(0), feat(0), pt, toff,
+                                      cxr, cyr);
+    __syncthreads();
+    floatx4 acc[R][NTV];
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+      for (int q = 0; q < NTV; ++q) acc[t][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    while (ch0.valid) {
+      const Chunk ch2 = walker_take(wk);
+      if (mma) {
+        const float* gx = tab(c & 1);
+        const float* gy = tab(c & 1) + kCols * KSF;
+        const float* bs = bas(c & 1);
+        const __bf16* G = feat(c & 1);
+#pragma unroll
+        for (int ks = 0; ks < KT; ks += 32) {
+          bf16x8 ahi[R], alo[R];
+          // one point at a time: its basis values and column factor, then
+          // the effective weight of each of the lane's nodes
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int k = ks + k8 + q;
+            float bj[m];
+#pragma unroll
+            for (int j = 0; j < m; ++j) bj[j] = bs[j * KSF + k];
+            const float wxq = gx[i * KSF + k];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+              float sh = yv[t][0] * bj[0];
+#pragma unroll
+              for (int j = 1; j < m; ++j) sh = fmaf(yv[t][j], bj[j], sh);
+              const float w = (wxq * gy[(wave * R + t) * KSF + k]) * sh;
+              const __bf16 hw = (__bf16)w;
+              ahi[t][q] = hw;
+              alo[t][q] = (__bf16)(w - (float)hw);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NTV; ++q) {
+            const bf16x8 b1 = *(const bf16x8*)(G + ((size_t)q * 16 + i) * KSH + ks + k8);
+            const bf16x8 b2 =
+                *(const bf16x8*)(G + ((size_t)L::kDs + q * 16 + i) * KSH + ks + k8);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+              acc[t][q] = mfma16(ahi[t], b1, acc[t][q]);
+              acc[t][q] = mfma16(alo[t], b1, acc[t][q]);
+              acc[t][q] = mfma16(ahi[t], b2, acc[t][q]);
+            }
+          }
+        }
+      } else {
+        shape_raw_load<L::kRawIt>(p, ch2, d0, nv, pt, rr);
+        if (ch1.valid)
+          shape_chunk<DEG, NTV, S1, true>(p, raw((c + 1) & 1), ch1.kn, nv, tab((c + 1) & 1),
+                                          bas((c + 1) & 1), feat((c + 1) & 1), pt, toff, cxr,
+                                          cyr);
+        shape_raw_store<L::kRawIt>(raw(c & 1), nv, pt, rr);
+      }
+      __syncthreads();
+      ch0 = ch1;
+      ch1 = ch2;
+      ++c;
+    }
+    // fields: the accumulators are the normalised values; lane holds node
+    // columns 4 (lane / 16) + r of strip t for attribute q * 16 + lane % 16
+    if (mma) {
+#pragma unroll
+      for (int q = 0; q < NTV; ++q) {
+        const int dd = q * 16 + (lane & 15);
+        if (dd >= nv) continue;
+        const double sh = (double)p.shift[d0 + dd], sc = (double)p.scale[d0 + dd];
+        float* fd = p.fields + (int64_t)(d0 + dd) * plane;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int row = wave * R + t, rg = r0 + row;
+          if (rg >= p.H) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int col = 4 * (lane >> 4) + r, cg = c0 + col;
+            if (cg >= p.W) continue;
+            const bool und = codes[row * kCols + col] == 255;
+            fd[(int64_t)rg * p.W + cg] =
+                und ? __builtin_nanf("") : (float)(sh + sc * (double)acc[t][q][r]);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int DEG, int NTV, int S1>
+hipError_t launch_shape_impl(const LPParams& p, hipStream_t s) {
+  using L = ShapeLayout<DEG, NTV, S1>;
+  const size_t lds = (size_t)L::kBytes;
+  const void* fn = (const void*)fit_shape_kernel<DEG, NTV, S1>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (int64_t)p.tiles * p.nslab;
+  hipLaunchKernelGGL((fit_shape_kernel<DEG, NTV, S1>), dim3((unsigned)blocks), dim3(kThreads), lds,
+                     s, p);
+  return hipGetLastError();
+}
+
+template <int DEG, int S1>
+hipError_t launch_shape_ntv(const LPParams& p, int ntv, hipStream_t s) {
+  switch (ntv) {
+    case 1: return launch_shape_impl<DEG, 1, S1>(p, s);
+    case 2: return launch_shape_impl<DEG, 2, S1>(p, s);
+    case 3: return launch_shape_impl<DEG, 3, S1>(p, s);
+    default: return launch_shape_impl<DEG, 4, S1>(p, s);
+  }
+}
+
+template <int S1>
+hipError_t launch_shape_deg(const LPParams& p, int deg, int ntv, hipStream_t s) {
+  return deg == 1 ? launch_shape_ntv<1, S1>(p, ntv, s) : launch_shape_ntv<2, S1>(p, ntv, s);
+}
+
 template <int DEG, int NTS, int S, typename T, bool WEND>
 hipError_t launch_lp_impl(LPParams p, hipStream_t s) {
   using L = LPLayout<DEG, NTS, S, T>;
@@ -577,9 +1042,64 @@ double lp_tile_extent(double dx, double dy, double h) {
   return ex > ey ? ex : ey;
 }
 
+bool lp_use_shape_form(int degree, int D, bool fp16, int wkind, bool grads, int terms,
+                       int forced_ds, int form) {
+  if (fp16 || wkind != 0 || grads || degree < 1) return false;
+  if (form == 1) return false;
+  if (form == 2) return true;
+  // the library's choice: the two-pass form once the one-pass form would
+  // issue at least twice its matrix instructions
+  int nts, ds, nslab;
+  lp_slab_plan(degree, D, forced_ds, &nts, &ds, &nslab);
+  const int one = nslab * nts * (2 * terms - 1);
+  const int nslab2 = (D + kShapeDsCap - 1) / kShapeDsCap;
+  const int per2 = (D + nslab2 - 1) / nslab2;
+  const int two = nslab2 * ((2 * terms - 1) + 3 * ((per2 + 15) / 16));
+  return one >= 2 * two;
+}
+
 hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shift,
                          const float* scale, bool fp16, int terms, const LPCells* cells,
                          hipStream_t stream) {
+  // the form depends on the request, not on the slab width (a tuning knob
+  // that must not change a result bit)
+  if (lp_use_shape_form(a.degree, a.D, fp16, a.wkind, a.grads != nullptr, terms, 0,
+                        a.lp_form)) {
+    LPParams p{};
+    p.pts = a.pts;
+    p.vals_t = vals_t;
+    p.shift = shift;
+    p.scale = scale;
+    p.n = a.n;
+    p.D = a.D;
+    p.nslab = (a.D + kShapeDsCap - 1) / kShapeDsCap;
+    p.Ds = (a.D + p.nslab - 1) / p.nslab;
+    p.inv_hd = 1.0 / a.h;
+    p.inv_h = (float)p.inv_hd;
+    p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;
+    p.W = a.W; p.H = a.H;
+    p.tiles_x = (a.W + kCols - 1) / kCols;
+    p.tiles = p.tiles_x * ((a.H + kRows - 1) / kRows);
+    p.tau = a.tau;
+    p.floor_w = a.floor_w;
+    const double sxd = a.dx / a.h, syd = a.dy / a.h;
+    const double half = 0.5 * sqrt((double)(kCols * kCols) * sxd * sxd +
+                                   (double)(kRows * kRows) * syd * syd);
+    const double reach = 8.0 + half;
+    p.cutoff2 = (float)(reach * reach);
+    p.fields = a.fields;
+    p.deg_out = a.deg_out;
+    p.grads = nullptr;
+    p.torder = nullptr;
+    p.tile_start = nullptr;
+    p.tile_list = nullptr;
+    const int ntv = (p.Ds + 15) / 16;
+    switch (terms) {
+      case 1: return launch_shape_deg<1>(p, a.degree, ntv, stream);
+      case 2: return launch_shape_deg<2>(p, a.degree, ntv, stream);
+      default: return launch_shape_deg<3>(p, a.degree, ntv, stream);
+    }
+  }
   int nts, ds, nslab;
   lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
   LPParams p;

@@ -22,6 +22,7 @@ struct FitArgs {
   float* fields;        // [D][H][W]
   uint8_t* deg_out;     // [H][W] or null
   int32_t lp_slab;      // 16-bit paths: attributes per slab, 0 = lp_slab_plan's choice
+  int32_t lp_form;      // 16-bit paths: 0 the library's choice, 1 one pass, 2 two passes
   float* grads;         // [D][2][H][W] slopes of the local fits, or null
   bool rigid;           // rigid map of 2-vector values (degree 1 moments, D = 2)
 };
@@ -47,6 +48,9 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
 // Attribute slabs of the 16-bit kernel: `forced_ds` attributes per slab
 // (0 = the cost model's choice); NTS feature tiles of 16 per slab.
 void lp_slab_plan(int degree, int D, int forced_ds, int* nts, int* ds, int* nslab);
+// Whether the 16-bit fit runs in the two-pass (shape-function) form.
+bool lp_use_shape_form(int degree, int D, bool fp16, int wkind, bool grads, int terms,
+                       int forced_ds, int form);
 // Largest attributes per slab the kernel supports for a degree.
 int lp_max_slab(int degree);
 // Largest node offset across a 16 x 16 node tile, in units of h.

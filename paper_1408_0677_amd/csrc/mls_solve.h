@@ -49,6 +49,124 @@ __device__ __forceinline__ double shift_entry(int r, int c, double ex, double ey
   }
 }
 
+// The degree ladder at one node: the tile-frame moments g[0 .. nmom) are
+// shifted to the node (M_p = T M_t T^T), then for k' = DEG, DEG-1, .. 0 the
+// equilibrated matrix S M_p' S is factored (L, every pivot >= tau) until a
+// degree is accepted.  Fills the factor and y = T'^T M_p'^{-1} e_0, the
+// tile-frame coefficients of the node's shape function: the fitted value
+// is y^T R_t.  Returns the accepted degree, or 255 when the weight sum
+// (divided by wscale) is below the floor or no degree is accepted.
+template <int DEG>
+struct Ladder {
+  static constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
+  double T[m][m], L[m][m], s[m], q[m], w[m], y[m];
+  int mk;
+};
+
+template <int DEG, typename Acc>
+__device__ __forceinline__ int ladder_solve(const Acc* g, double ex, double ey, double tau,
+                                            double floor_w, double wscale, Ladder<DEG>& lad) {
+  constexpr int m = Ladder<DEG>::m;
+  const double sumw = (double)g[0] / wscale;
+  if (!(sumw >= floor_w)) return 255;
+  double Mt[m][m];
+#pragma unroll
+  for (int j = 0; j < m; ++j)
+#pragma unroll
+    for (int k = 0; k < m; ++k)
+      Mt[j][k] = (double)g[mono_index(basis_ax(j) + basis_ax(k), basis_ay(j) + basis_ay(k))];
+#pragma unroll
+  for (int r = 0; r < m; ++r)
+#pragma unroll
+    for (int c = 0; c < m; ++c) lad.T[r][c] = shift_entry(r, c, ex, ey);
+  // Mp = T Mt T^T (lower triangle is all the ladder reads)
+  double TM[m][m];
+#pragma unroll
+  for (int r = 0; r < m; ++r)
+#pragma unroll
+    for (int c = 0; c < m; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= r; ++q) v += lad.T[r][q] * Mt[q][c];
+      TM[r][c] = v;
+    }
+  double Mp[m][m];
+#pragma unroll
+  for (int r = 0; r < m; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= c; ++q) v += TM[r][q] * lad.T[c][q];
+      Mp[r][c] = v;
+    }
+#pragma unroll
+  for (int kd = DEG; kd >= 0; --kd) {
+    const int mk = kd == 0 ? 1 : (kd == 1 ? 3 : 6);
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      if (j < mk) {
+        ok = ok && (Mp[j][j] > 0.0);
+        lad.s[j] = ok ? 1.0 / sqrt(Mp[j][j]) : 0.0;
+      }
+    }
+    if (!ok) continue;
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      if (j >= mk || !ok) continue;
+      double piv = lad.s[j] * Mp[j][j] * lad.s[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) piv -= lad.L[j][q] * lad.L[j][q];
+      if (!(piv >= tau)) {
+        ok = false;
+        continue;
+      }
+      lad.L[j][j] = sqrt(piv);
+      const double inv = 1.0 / lad.L[j][j];
+#pragma unroll
+      for (int r = j + 1; r < m; ++r) {
+        if (r >= mk) continue;
+        double v = lad.s[r] * Mp[r][j] * lad.s[j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) v -= lad.L[r][q] * lad.L[j][q];
+        lad.L[r][j] = v * inv;
+      }
+    }
+    if (!ok) continue;
+    // z = S A^{-1} S e0:  L q = s0 e0,  L^T w = q,  z = S w
+#pragma unroll
+    for (int r = 0; r < m; ++r) {
+      if (r >= mk) continue;
+      double v = r == 0 ? lad.s[0] : 0.0;
+#pragma unroll
+      for (int c = 0; c < r; ++c) v -= lad.L[r][c] * lad.q[c];
+      lad.q[r] = v / lad.L[r][r];
+    }
+#pragma unroll
+    for (int r = m - 1; r >= 0; --r) {
+      if (r >= mk) continue;
+      double v = lad.q[r];
+#pragma unroll
+      for (int c = r + 1; c < m; ++c)
+        if (c < mk) v -= lad.L[c][r] * lad.w[c];
+      lad.w[r] = v / lad.L[r][r];
+    }
+    // y = T'^T z over the accepted rows
+#pragma unroll
+    for (int c = 0; c < m; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < m; ++r)
+        if (r < mk) v += lad.T[r][c] * (lad.s[r] * lad.w[r]);
+      lad.y[c] = v;
+    }
+    lad.mk = mk;
+    return kd;
+  }
+  return 255;   // only when sum w == 0 passes a zero floor
+}
+
 // Solve one node.  `g` points at the node's F accumulated features
 // (consecutive values, float64 or float32), `ex, ey` is delta.  Writes
 // field_d to fields[d * plane] (float32) and returns the accepted degree
@@ -64,171 +182,66 @@ __device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, do
                               int64_t plane, const float* shift = nullptr,
                               const float* scale = nullptr, double wscale = 1.0,
                               float* grads = nullptr, double inv_h = 1.0) {
-  constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
+  constexpr int m = Ladder<DEG>::m;
   constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
-  const double sumw = (double)g[0] / wscale;
-  if (!(sumw >= floor_w)) {
+  Ladder<DEG> lad;
+  const int accepted = ladder_solve<DEG>(g, ex, ey, tau, floor_w, wscale, lad);
+  if (accepted == 255) {
     for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
     if (grads)
       for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane] = __builtin_nan("");
     return 255;
   }
-  double Mt[m][m];
-#pragma unroll
-  for (int j = 0; j < m; ++j)
-#pragma unroll
-    for (int k = 0; k < m; ++k)
-      Mt[j][k] = (double)g[mono_index(basis_ax(j) + basis_ax(k), basis_ay(j) + basis_ay(k))];
-  double T[m][m];
-#pragma unroll
-  for (int r = 0; r < m; ++r)
-#pragma unroll
-    for (int c = 0; c < m; ++c) T[r][c] = shift_entry(r, c, ex, ey);
-  // Mp = T Mt T^T (lower triangle is all the ladder reads)
-  double TM[m][m];
-#pragma unroll
-  for (int r = 0; r < m; ++r)
-#pragma unroll
-    for (int c = 0; c < m; ++c) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q <= r; ++q) v += T[r][q] * Mt[q][c];
-      TM[r][c] = v;
-    }
-  double Mp[m][m];
-#pragma unroll
-  for (int r = 0; r < m; ++r)
-#pragma unroll
-    for (int c = 0; c <= r; ++c) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q <= c; ++q) v += TM[r][q] * T[c][q];
-      Mp[r][c] = v;
-    }
-
-  double y[m];
-  int accepted = -1;
-#pragma unroll
-  for (int kd = DEG; kd >= 0; --kd) {
-    const int mk = kd == 0 ? 1 : (kd == 1 ? 3 : 6);
-    double s[m], L[m][m];
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < m; ++j) {
-      if (j < mk) {
-        ok = ok && (Mp[j][j] > 0.0);
-        s[j] = ok ? 1.0 / sqrt(Mp[j][j]) : 0.0;
-      }
-    }
-    if (!ok) continue;
-#pragma unroll
-    for (int j = 0; j < m; ++j) {
-      if (j >= mk || !ok) continue;
-      double piv = s[j] * Mp[j][j] * s[j];
-#pragma unroll
-      for (int q = 0; q < j; ++q) piv -= L[j][q] * L[j][q];
-      if (!(piv >= tau)) {
-        ok = false;
-        continue;
-      }
-      L[j][j] = sqrt(piv);
-      const double inv = 1.0 / L[j][j];
-#pragma unroll
-      for (int r = j + 1; r < m; ++r) {
-        if (r >= mk) continue;
-        double v = s[r] * Mp[r][j] * s[j];
-#pragma unroll
-        for (int q = 0; q < j; ++q) v -= L[r][q] * L[j][q];
-        L[r][j] = v * inv;
-      }
-    }
-    if (!ok) continue;
-    // z = S A^{-1} S e0:  L q = s0 e0,  L^T w = q,  z = S w
-    double q[m], w[m];
-#pragma unroll
-    for (int r = 0; r < m; ++r) {
-      if (r >= mk) continue;
-      double v = r == 0 ? s[0] : 0.0;
-#pragma unroll
-      for (int c = 0; c < r; ++c) v -= L[r][c] * q[c];
-      q[r] = v / L[r][r];
-    }
-#pragma unroll
-    for (int r = m - 1; r >= 0; --r) {
-      if (r >= mk) continue;
-      double v = q[r];
-#pragma unroll
-      for (int c = r + 1; c < m; ++c)
-        if (c < mk) v -= L[c][r] * w[c];
-      w[r] = v / L[r][r];
-    }
-    // y = T'^T z over the accepted rows
-#pragma unroll
-    for (int c = 0; c < m; ++c) {
-      double v = 0.0;
-#pragma unroll
-      for (int r = 0; r < m; ++r)
-        if (r < mk) v += T[r][c] * (s[r] * w[r]);
-      y[c] = v;
-    }
-    if (grads) {
-      // slopes: the same two triangular solves with S e_1 and S e_2
-      const Acc* Rg = g + nmom;
+  const int mk = lad.mk;
+  if (grads) {
+    // slopes: the same two triangular solves with S e_1 and S e_2
+    const Acc* Rg = g + nmom;
 #pragma unroll 1
-      for (int a = 1; a <= 2; ++a) {
-        double ya[m];
+    for (int a = 1; a <= 2; ++a) {
+      double ya[m];
 #pragma unroll
-        for (int c = 0; c < m; ++c) ya[c] = 0.0;
-        if (mk >= 3) {
+      for (int c = 0; c < m; ++c) ya[c] = 0.0;
+      if (mk >= 3) {
 #pragma unroll
-          for (int r = 0; r < m; ++r) {
-            if (r >= mk) continue;
-            double v = r == a ? s[r] : 0.0;
+        for (int r = 0; r < m; ++r) {
+          if (r >= mk) continue;
+          double v = r == a ? lad.s[r] : 0.0;
 #pragma unroll
-            for (int c = 0; c < r; ++c) v -= L[r][c] * q[c];
-            q[r] = v / L[r][r];
-          }
-#pragma unroll
-          for (int r = m - 1; r >= 0; --r) {
-            if (r >= mk) continue;
-            double v = q[r];
-#pragma unroll
-            for (int c = r + 1; c < m; ++c)
-              if (c < mk) v -= L[c][r] * w[c];
-            w[r] = v / L[r][r];
-          }
-#pragma unroll
-          for (int c = 0; c < m; ++c) {
-            double v = 0.0;
-#pragma unroll
-            for (int r = 0; r < m; ++r)
-              if (r < mk) v += T[r][c] * (s[r] * w[r]);
-            ya[c] = v;
-          }
+          for (int c = 0; c < r; ++c) v -= lad.L[r][c] * lad.q[c];
+          lad.q[r] = v / lad.L[r][r];
         }
-        for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int r = m - 1; r >= 0; --r) {
+          if (r >= mk) continue;
+          double v = lad.q[r];
+#pragma unroll
+          for (int c = r + 1; c < m; ++c)
+            if (c < mk) v -= lad.L[c][r] * lad.w[c];
+          lad.w[r] = v / lad.L[r][r];
+        }
+#pragma unroll
+        for (int c = 0; c < m; ++c) {
           double v = 0.0;
 #pragma unroll
-          for (int c = 0; c < m; ++c) v += ya[c] * (double)Rg[c * D + d];
-          if (scale) v *= (double)scale[d];
-          grads[(int64_t)(2 * d + a - 1) * plane] = (float)(v * inv_h);
+          for (int r = 0; r < m; ++r)
+            if (r < mk) v += lad.T[r][c] * (lad.s[r] * lad.w[r]);
+          ya[c] = v;
         }
       }
+      for (int d = 0; d < D; ++d) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < m; ++c) v += ya[c] * (double)Rg[c * D + d];
+        if (scale) v *= (double)scale[d];
+        grads[(int64_t)(2 * d + a - 1) * plane] = (float)(v * inv_h);
+      }
     }
-    accepted = kd;
-    break;
-  }
-  if (accepted < 0) {  // only when sum w == 0 passes a zero floor
-    for (int d = 0; d < D; ++d) fields[(int64_t)d * plane] = __builtin_nan("");
-    if (grads)
-      for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane] = __builtin_nan("");
-    return 255;
   }
   const Acc* R = g + nmom;
   for (int d = 0; d < D; ++d) {
     double v = 0.0;
 #pragma unroll
-    for (int c = 0; c < m; ++c) v += y[c] * (double)R[c * D + d];
+    for (int c = 0; c < m; ++c) v += lad.y[c] * (double)R[c * D + d];
     if (shift) v = (double)shift[d] + (double)scale[d] * v;
     fields[(int64_t)d * plane] = (float)v;
   }

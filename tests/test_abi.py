@@ -229,3 +229,10 @@ def test_contour_static_arguments_rejected_before_device(lib):
     st = lib.mls_contour_static(None, fake, 1, ctypes.byref(g), fake, 2, None, fake, None, 10,
                                 fake, None)
     assert st == -1 and b"ctx is NULL" in lib.mls_last_error()
+
+
+def test_trace_arguments_rejected(lib):
+    from paper_1408_0677_amd import _lib
+    assert lib.mls_context_trace(None, 1, None) == -1
+    rec = _lib.MlsTraceRecord()
+    assert lib.mls_context_trace_last(None, ctypes.byref(rec)) == -1

@@ -317,3 +317,57 @@ def test_slab_width_bitwise_invariant(torch_dev, case):
                         precision=prec, lp_slab=ds)
         assert np.array_equal(dg, dref), ds
         assert np.array_equal(f.view(np.uint32), ref.view(np.uint32)), ds
+
+
+@pytest.mark.parametrize("basis", ["linear", "quadratic"])
+@pytest.mark.parametrize("shape", [(37, 29, 600, 3, 0.08), (130, 40, 3000, 41, 0.05),
+                                   (20, 18, 800, 70, 0.06), (1, 1, 400, 2, 0.1)])
+def test_shape_form_lp(torch_dev, oracle, basis, shape):
+    """The two-pass (shape-function) form of the bfloat16 path against the
+    oracle at the one-pass form's bounds: ragged tiles, one and two
+    attribute slabs (70 attributes), a single node."""
+    from paper_1408_0677_amd import workloads as wl
+    W, H, n, D, h = shape
+    note(f"case shape form basis={basis} W={W} H={H} n={n} D={D}")
+    rng = np.random.default_rng(W * 1000 + H + n + 7)
+    pts = rng.random((n, 2)) * 0.6 + 0.2
+    vals = wl.smooth_fields(rng, pts, D) * 3.0 + 10.0
+    grid = {"x0": 0.25, "y0": 0.25, "dx": 0.006, "dy": 0.007, "width": W, "height": H}
+    F, deg = gpu_fit(torch_dev, pts, vals, grid, basis=basis, h=h, precision="bf16", lp_form=2)
+    of, od, dm = oracle.fit_grid(pts, vals, grid, basis=basis, h=h)
+    st = compare(F.reshape(D, -1), deg, of.reshape(D, -1), od, dm, vals.astype(np.float32),
+                 dmin_pass=1e-2)
+    check_lp(st, "bf16", 3)
+
+
+def test_shape_form_clustered(torch_dev, oracle):
+    """Both forms on the clustered, noisy quadratic case: the same bound,
+    and the two-pass error no larger than twice the one-pass error (the
+    moments' float32 sums dominate both)."""
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c2(grid_side=256, n=2000)
+    note("case shape form clustered")
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis="quadratic", h=0.06)
+    res = {}
+    for form in (1, 2):
+        F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis="quadratic", h=0.06,
+                         precision="bf16", lp_form=form)
+        st = compare(F.reshape(w.d, -1), deg, of.reshape(w.d, -1), od, dm, w.values,
+                     dmin_pass=1e-2)
+        note(f"form {form}: max {st['max_err_pass']:.3e} rms {st['rms_err_pass']:.3e} "
+             f"mismatches {st['degree_mismatch']}")
+        check_lp(st, "bf16", 3, max_bound=CLUSTERED_MAX)
+        res[form] = st
+    assert res[2]["rms_err_pass"] <= 2.0 * res[1]["rms_err_pass"]
+
+
+def test_shape_form_deterministic(torch_dev):
+    from paper_1408_0677_amd import workloads as wl
+    w = wl.c2(grid_side=128, n=3000)
+    note("case shape form determinism")
+    a, da = gpu_fit(torch_dev, w.points, w.values, w.grid, basis="quadratic", h=0.06,
+                    precision="bf16", lp_form=2)
+    b, db = gpu_fit(torch_dev, w.points, w.values, w.grid, basis="quadratic", h=0.06,
+                    precision="bf16", lp_form=2)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert np.array_equal(da, db)
