@@ -172,9 +172,13 @@ __device__ __forceinline__ double node_offset_yd(const LPParams& p, int r0, int 
   return (p.y0 + (double)(r0 + row) * p.dy - (double)cyr) * p.inv_hd;
 }
 
-// Wendland C2 weight (1 - s)^4 (4 s + 1) for s = r / h < 1, from s^2.
+// Wendland C2 weight (1 - s)^4 (4 s + 1) for s = r / h < 1, from s^2.  The
+// hardware square root (about 1 ulp) replaces the correctly rounded
+// sequence, which costs eight more instructions per pair: the weight is
+// carried as hi + lo bfloat16 terms, about 17 bits, and any rounding of it
+// is common to every feature of the pair.
 __device__ __forceinline__ float wendland_c2(float s2) {
-  const float s = __builtin_sqrtf(s2);
+  const float s = __builtin_amdgcn_sqrtf(s2);
   const float t = 1.0f - s;
   const float t2 = t * t;
   return s < 1.0f ? t2 * t2 * (4.0f * s + 1.0f) : 0.0f;
@@ -448,19 +452,21 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
         }
   }
   __syncthreads();
-  if (mma) {
-    const float* e = epi + wave * 16 * R * L::kEpiStride;
+  // one node per lane on the first four waves (one per SIMD): the float64
+  // solve is issued by four full waves rather than eight half-empty ones
+  if (tid < kRows * kCols) {
+    const int w = tid / (16 * R), local = tid % (16 * R);
+    const float* e = epi + (w * 16 * R + local) * L::kEpiStride;
     const int64_t plane = (int64_t)p.W * p.H;
-    for (int node = lane; node < 16 * R; node += 64) {
-      const int t = node / 16, col = node % 16;
-      const int r = r0 + wave * R + t, cc = c0 + col;
-      if (r >= p.H || cc >= p.W) continue;
+    const int t = local / 16, col = local % 16;
+    const int r = r0 + w * R + t, cc = c0 + col;
+    if (r < p.H && cc < p.W) {
       const double ex = node_offset_xd(p, c0, col, cxr);
-      const double ey = node_offset_yd(p, r0, wave * R + t, cyr);
+      const double ey = node_offset_yd(p, r0, w * R + t, cyr);
       const int64_t off = (int64_t)r * p.W + cc;
-      uint8_t code = solve_node<DEG, float>(e + node * L::kEpiStride, Ds, ex, ey, p.tau,
-                                            p.floor_w, p.fields + (int64_t)d0 * plane + off,
-                                            plane, p.shift + d0, p.scale + d0,
+      uint8_t code = solve_node<DEG, float>(e, Ds, ex, ey, p.tau, p.floor_w,
+                                            p.fields + (int64_t)d0 * plane + off, plane,
+                                            p.shift + d0, p.scale + d0,
                                             (double)WeightGain<T>::value,
                                             p.grads ? p.grads + (int64_t)(2 * d0) * plane + off
                                                     : nullptr,
@@ -765,24 +771,23 @@ __global__ __launch_bounds__(kThreads) void fit_shape_kernel(LPParams p) {
           e[(t * 16 + 4 * (lane >> 4) + r) * L::kEpiStride + (lane & 15)] = acc[t][r];
     }
     __syncthreads();
-    if (mma) {
-      const float* e = epi + wave * 16 * R * L::kEpiStride;
-      for (int node = lane; node < 16 * R; node += 64) {
-        const int t = node / 16, col = node % 16;
-        const int row = wave * R + t;
-        const double ex = node_offset_xd(p, c0, col, cxr);
-        const double ey = node_offset_yd(p, r0, row, cyr);
-        Ladder<DEG> lad;
-        const int code = ladder_solve<DEG>(e + node * L::kEpiStride, ex, ey, p.tau, p.floor_w,
-                                           1.0, lad);
-        float* yv = ybuf + (row * kCols + col) * m;
+    // one node per lane on the first four waves (one per SIMD)
+    if (tid < kRows * kCols) {
+      const int w = tid / (16 * R), local = tid % (16 * R);
+      const float* e = epi + (w * 16 * R + local) * L::kEpiStride;
+      const int t = local / 16, col = local % 16;
+      const int row = w * R + t;
+      const double ex = node_offset_xd(p, c0, col, cxr);
+      const double ey = node_offset_yd(p, r0, row, cyr);
+      Ladder<DEG> lad;
+      const int code = ladder_solve<DEG>(e, ex, ey, p.tau, p.floor_w, 1.0, lad);
+      float* yv = ybuf + (row * kCols + col) * m;
 #pragma unroll
-        for (int j = 0; j < m; ++j) yv[j] = code == 255 ? 0.0f : (float)lad.y[j];
-        codes[row * kCols + col] = (uint8_t)code;
-        const int rr2 = r0 + row, cc = c0 + col;
-        if (p.deg_out && slab == 0 && rr2 < p.H && cc < p.W)
-          p.deg_out[(int64_t)rr2 * p.W + cc] = (uint8_t)code;
-      }
+      for (int j = 0; j < m; ++j) yv[j] = code == 255 ? 0.0f : (float)lad.y[j];
+      codes[row * kCols + col] = (uint8_t)code;
+      const int rr2 = r0 + row, cc = c0 + col;
+      if (p.deg_out && slab == 0 && rr2 < p.H && cc < p.W)
+        p.deg_out[(int64_t)rr2 * p.W + cc] = (uint8_t)code;
     }
     __syncthreads();
   }
