@@ -279,6 +279,7 @@ FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, do
       p.o_perm = carve(4 * (size_t)n);
       p.o_perm2 = carve(4 * (size_t)n);
       p.o_hist = carve(4 * 256 * (size_t)radix_blocks(n));
+      p.o_ssum = carve(4 * (size_t)scan_sums_words(256 * radix_blocks(n)));
     }
     p.total = off;
     return p;
@@ -322,7 +323,14 @@ FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, do
     p.o_vals_s = carve(4 * (size_t)n * (size_t)d);
     p.o_tk = carve(4 * (size_t)p.tiles);
     p.o_tk2 = carve(4 * (size_t)p.tiles);
-    p.o_to = carve(4 * (size_t)p.tiles);
+    p.order_slots = tile_order_slots(p.tiles_x, p.tiles / p.tiles_x);
+    p.o_to = carve(4 * (size_t)p.order_slots);
+    p.o_so = carve(4 * (size_t)p.tiles);
+    int64_t scan_max = 256 * nrb;
+    if (ncells + 1 > scan_max) scan_max = ncells + 1;
+    if (p.tiles + 1 > scan_max) scan_max = p.tiles + 1;
+    if (256 * trb > scan_max) scan_max = 256 * trb;
+    p.o_ssum = carve(4 * (size_t)scan_sums_words(scan_max));
     p.o_to2 = carve(4 * (size_t)p.tiles);
     p.o_th = carve(4 * 256 * (size_t)trb);
     p.o_ts = carve(4 * (size_t)(p.tiles + 1));
@@ -551,6 +559,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       hta.idx = (uint32_t*)(base + plan.o_perm);
       hta.idx2 = (uint32_t*)(base + plan.o_perm2);
       hta.hist = (uint32_t*)(base + plan.o_hist);
+      hta.ssum = (uint32_t*)(base + plan.o_ssum);
       e = mls::launch_hits(hta, s);
       if (e != hipSuccess) return device_fail(e, "exact-hit pass launch");
       tr.mark("hits");
@@ -633,6 +642,8 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   ca.tkeys2 = (uint32_t*)(base + plan.o_tk2);
   ca.torder2 = (uint32_t*)(base + plan.o_to2);
   ca.thist = (uint32_t*)(base + plan.o_th);
+  ca.sorder = (uint32_t*)(base + plan.o_so);
+  ca.ssum = (uint32_t*)(base + plan.o_ssum);
   ca.tile_start = (uint32_t*)(base + plan.o_ts);
   ca.tile_list = (uint32_t*)(base + plan.o_tl);
   ca.list_cap = plan.list_cap;

@@ -19,7 +19,8 @@
 // the tile's support reaches, so a tile's fit touches no point that cannot
 // weigh in; the cells alone hold 2-4x more), and a second sort that orders
 // node tiles by descending list length, so that the heavy tiles of dense
-// clusters start first.
+// clusters start first; the order keeps 4 x 4 supertiles of neighbouring
+// tiles together on one XCD, so that their shared points stay in its L2.
 // All of it is bound by HBM and launch latency, not arithmetic.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -53,17 +54,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
   hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of `count` uint32 values in place, one block of 1024
-// threads (sequential runs per thread, then a block scan of the run sums).
-__global__ __launch_bounds__(1024) void scan_u32_kernel(uint32_t* v, int64_t count,
-                                                        uint32_t* total) {
-  __shared__ uint32_t wsum[16];
+// Multi-block exclusive scan, in place: each block scans 1024 values and
+// writes its total; then each block adds the sum of the totals before it.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(256) void scan_blocks_u32_kernel(uint32_t* v, int64_t count,
+                                                              uint32_t* sums) {
+  __shared__ uint32_t wsum[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t per = (count + 1023) / 1024;
-  const int64_t lo = t * per, hi = lo + per < count ? lo + per : count;
-  uint32_t s = 0;
-  for (int64_t q = lo; q < hi; ++q) s += v[q];
-  uint32_t incl = s;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + 4 * t;
+  uint32_t x[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    x[q] = base + q < count ? v[base + q] : 0u;
+    sum += x[q];
+  }
+  uint32_t incl = sum;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t nb = __shfl_up(incl, o, 64);
@@ -71,18 +77,35 @@ __global__ __launch_bounds__(1024) void scan_u32_kernel(uint32_t* v, int64_t cou
   }
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  uint32_t wbase = 0, tot = 0;
-  for (int w = 0; w < 16; ++w) {
-    if (w < wave) wbase += wsum[w];
+  uint32_t run = incl - sum, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) run += wsum[w];
     tot += wsum[w];
   }
-  uint32_t run = wbase + incl - s;
-  for (int64_t q = lo; q < hi; ++q) {
-    const uint32_t x = v[q];
-    v[q] = run;
-    run += x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < count) v[base + q] = run;
+    run += x[q];
   }
-  if (t == 0 && total) *total = tot;
+  if (t == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan_add_u32_kernel(uint32_t* v, int64_t count,
+                                                           const uint32_t* sums) {
+  __shared__ uint32_t wsum[4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int b = blockIdx.x;
+  uint32_t s = 0;
+  for (int j = t; j < b; j += 256) s += sums[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) wsum[wave] = s;
+  __syncthreads();
+  const uint32_t prefix = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  const int64_t base = (int64_t)b * kScanBlock;
+  for (int q = t; q < kScanBlock; q += 256)
+    if (base + q < count) v[base + q] += prefix;
 }
 
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
@@ -155,10 +178,19 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* p, int64_t n, u
   if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void cell_count_kernel(const uint32_t* sorted_keys, int64_t n,
-                                                         uint32_t* counts) {
+// cell_start from the sorted cell ids: the first point of each run of ids
+// writes its index into the start of every cell from the previous run's id
+// + 1 up to its own (empty cells between take the same start); the last
+// point closes the cells after it.  No atomics.
+__global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t* sorted_keys, int64_t n,
+                                                         int64_t ncells, uint32_t* cell_start) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) atomicAdd(&counts[sorted_keys[i]], 1u);
+  if (i >= n) return;
+  const int64_t k = sorted_keys[i];
+  const int64_t prev = i == 0 ? -1 : (int64_t)sorted_keys[i - 1];
+  for (int64_t c = prev + 1; c <= k; ++c) cell_start[c] = (uint32_t)i;
+  if (i == n - 1)
+    for (int64_t c = k + 1; c <= ncells; ++c) cell_start[c] = (uint32_t)n;
 }
 
 // Sorted payload: coordinates and the attribute-major normalised values.
@@ -182,6 +214,45 @@ __global__ __launch_bounds__(256) void gather_values_kernel(const float* vals_t,
 __global__ __launch_bounds__(256) void iota_u32_kernel(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = (uint32_t)i;
+}
+
+// Work of each 4 x 4 supertile (the sum of its tiles' list lengths, from
+// the scanned list starts), as a descending sort key; iota of the ids.
+__global__ __launch_bounds__(256) void supertile_work_kernel(const uint32_t* tile_start,
+                                                             int tiles_x, int tiles_y,
+                                                             int super_x, int nsuper,
+                                                             uint32_t* keys, uint32_t* ids) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= nsuper) return;
+  const int sx = s % super_x, sy = s / super_x;
+  uint64_t work = 0;
+  for (int k = 0; k < kSuperTile * kSuperTile; ++k) {
+    const int tc = sx * kSuperTile + k % kSuperTile, tr = sy * kSuperTile + k / kSuperTile;
+    if (tc < tiles_x && tr < tiles_y) {
+      const int t = tr * tiles_x + tc;
+      work += tile_start[t + 1] - tile_start[t];
+    }
+  }
+  keys[s] = 0xFFFFFFFFu - (work > 0xFFFFFFFEull ? 0xFFFFFFFEu : (uint32_t)work);
+  ids[s] = (uint32_t)s;
+}
+
+// Supertile of rank j (heaviest first) goes to XCD j % 8, as its slot
+// j / 8 there; its tiles take 16 consecutive workgroups of that XCD
+// (workgroup b runs on XCD b % 8).
+__global__ __launch_bounds__(256) void tile_slots_kernel(const uint32_t* sorder, int tiles_x,
+                                                         int tiles_y, int super_x, int nsuper,
+                                                         uint32_t* torder) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int kPer = kSuperTile * kSuperTile;
+  const int64_t j = i / kPer;
+  const int k = (int)(i % kPer);
+  if (j >= nsuper) return;
+  const int s = (int)sorder[j];
+  const int tc = (s % super_x) * kSuperTile + k % kSuperTile;
+  const int tr = (s / super_x) * kSuperTile + k / kSuperTile;
+  const int64_t slot = 8 * (kPer * (j / 8) + k) + j % 8;
+  torder[slot] = (tc < tiles_x && tr < tiles_y) ? (uint32_t)(tr * tiles_x + tc) : 0xFFFFFFFFu;
 }
 
 // Per-tile point lists.  One wave per node tile walks the cell runs the
@@ -259,17 +330,27 @@ int64_t tile_list_bound(int64_t n, double h, double dx, double dy, int tiles_x, 
 
 int64_t radix_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
+int64_t scan_sums_words(int64_t count) { return (count + kScanBlock - 1) / kScanBlock; }
+
+hipError_t scan_u32(uint32_t* v, int64_t count, uint32_t* sums, hipStream_t s) {
+  const unsigned nb = (unsigned)scan_sums_words(count);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_blocks_u32_kernel, dim3(nb), dim3(256), 0, s, v, count, sums);
+  hipLaunchKernelGGL(scan_add_u32_kernel, dim3(nb), dim3(256), 0, s, v, count,
+                     (const uint32_t*)sums);
+  return hipGetLastError();
+}
+
 // Stable sort of (key, val) pairs by the low `bits` bits of key.  On return
 // the result is in (k0, v0); (k1, v1) are scratch of the same size; hist
 // holds 256 * radix_blocks(n) words.
 hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                            int bits, uint32_t* hist, hipStream_t s) {
+                            int bits, uint32_t* hist, uint32_t* sums, hipStream_t s) {
   const int nblk = (int)radix_blocks(n);
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nblk), dim3(kSortThreads), 0, s, k0, n, shift,
                        hist, nblk);
-    hipLaunchKernelGGL(scan_u32_kernel, dim3(1), dim3(1024), 0, s, hist,
-                       (int64_t)kDigits * nblk, (uint32_t*)nullptr);
+    scan_u32(hist, (int64_t)kDigits * nblk, sums, s);
     hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nblk), dim3(kSortThreads), 0, s, k0, v0, n,
                        shift, hist, nblk, k1, v1);
     uint32_t* tk = k0; k0 = k1; k1 = tk;
@@ -292,13 +373,10 @@ hipError_t launch_cells(const CellArgs& a, hipStream_t s) {
   int bits = 0;
   while ((1 << bits) < ncells) ++bits;
   if (bits < 8) bits = 8;
-  hipError_t e = radix_sort_pairs(a.keys, a.perm, a.keys2, a.perm2, n, bits, a.hist, s);
+  hipError_t e = radix_sort_pairs(a.keys, a.perm, a.keys2, a.perm2, n, bits, a.hist, a.ssum, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((ncells + 1 + 255) / 256)), dim3(256), 0, s,
-                     a.cell_start, (int64_t)ncells + 1, 0u);
-  hipLaunchKernelGGL(cell_count_kernel, dim3(gb), dim3(256), 0, s, a.keys, n, a.cell_start);
-  hipLaunchKernelGGL(scan_u32_kernel, dim3(1), dim3(1024), 0, s, a.cell_start,
-                     (int64_t)ncells + 1, (uint32_t*)nullptr);
+  hipLaunchKernelGGL(cell_start_kernel, dim3(gb), dim3(256), 0, s, a.keys, n, (int64_t)ncells,
+                     a.cell_start);
   hipLaunchKernelGGL(gather_points_kernel, dim3(gb), dim3(256), 0, s, a.pts, a.perm, n, a.pts_s);
   hipLaunchKernelGGL(gather_values_kernel, dim3(gb, a.D), dim3(256), 0, s, a.vals_t, a.perm, n,
                      a.D, a.vals_ts);
@@ -309,16 +387,25 @@ hipError_t launch_cells(const CellArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(tile_list_kernel, dim3(lb), dim3(256), 0, s, a.cell_start, a.pts_s, a.ncx,
                      a.ncy, a.geom, a.tiles_x, a.tiles, a.tile_start, a.tkeys,
                      (const uint32_t*)nullptr, (uint32_t*)nullptr, (int64_t)0);
-  hipLaunchKernelGGL(scan_u32_kernel, dim3(1), dim3(1024), 0, s, a.tile_start,
-                     (int64_t)a.tiles + 1, (uint32_t*)nullptr);
+  scan_u32(a.tile_start, (int64_t)a.tiles + 1, a.ssum, s);
   hipLaunchKernelGGL(tile_list_kernel, dim3(lb), dim3(256), 0, s, a.cell_start, a.pts_s, a.ncx,
                      a.ncy, a.geom, a.tiles_x, a.tiles, (uint32_t*)nullptr, (uint32_t*)nullptr,
                      (const uint32_t*)a.tile_start, a.tile_list, a.list_cap);
-  // tile order by descending work (list length)
-  const int tb = (a.tiles + 255) / 256;
-  hipLaunchKernelGGL(iota_u32_kernel, dim3(tb), dim3(256), 0, s, a.torder, (int64_t)a.tiles);
-  e = radix_sort_pairs(a.tkeys, a.torder, a.tkeys2, a.torder2, a.tiles, 32, a.thist, s);
-  return e != hipSuccess ? e : hipGetLastError();
+  // workgroup order: supertiles by descending work, dealt to the XCDs
+  const int tiles_y = a.tiles / a.tiles_x;
+  const int super_x = (a.tiles_x + kSuperTile - 1) / kSuperTile;
+  const int nsuper = super_x * ((tiles_y + kSuperTile - 1) / kSuperTile);
+  const int64_t slots = tile_order_slots(a.tiles_x, tiles_y);
+  hipLaunchKernelGGL(supertile_work_kernel, dim3((unsigned)((nsuper + 255) / 256)), dim3(256), 0,
+                     s, a.tile_start, a.tiles_x, tiles_y, super_x, nsuper, a.tkeys, a.sorder);
+  e = radix_sort_pairs(a.tkeys, a.sorder, a.tkeys2, a.torder2, nsuper, 32, a.thist, a.ssum, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, s,
+                     a.torder, slots, 0xFFFFFFFFu);
+  hipLaunchKernelGGL(tile_slots_kernel,
+                     dim3((unsigned)(((int64_t)nsuper * kSuperTile * kSuperTile + 255) / 256)),
+                     dim3(256), 0, s, a.sorder, a.tiles_x, tiles_y, super_x, nsuper, a.torder);
+  return hipGetLastError();
 }
 
 }  // namespace mls

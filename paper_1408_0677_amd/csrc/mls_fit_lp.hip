@@ -112,7 +112,8 @@ struct LPParams {
   float* fields;
   uint8_t* deg_out;
   float* grads;           // [D][2][H][W] or null
-  const uint32_t* torder;      // node tiles by descending work (Wendland)
+  const uint32_t* torder;      // tile of each workgroup slot (Wendland)
+  int slots;                   // workgroup slots per attribute slab (Wendland)
   const uint32_t* tile_start;  // per-tile point lists (Wendland): [tiles + 1]
   const uint32_t* tile_list;   //   cell-ordered point indices, or null
 };
@@ -327,8 +328,14 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool mma = wave < kMmaWaves;
   const int pt = tid - kMmaWaves * 64;   // producer thread index
-  const int slab = blockIdx.x / p.tiles;
-  const int tile = CELLS ? (int)p.torder[blockIdx.x % p.tiles] : (int)(blockIdx.x % p.tiles);
+  // with the cell list, p.slots workgroup slots per slab map to tiles
+  // through the supertile order; empty slots exit before any barrier
+  const int per_slab = CELLS ? p.slots : p.tiles;
+  const int slab = blockIdx.x / per_slab;
+  const uint32_t tile_u =
+      CELLS ? p.torder[blockIdx.x % per_slab] : (uint32_t)(blockIdx.x % per_slab);
+  if (tile_u == 0xFFFFFFFFu) return;
+  const int tile = (int)tile_u;
   const int c0 = (tile % p.tiles_x) * kCols;
   const int r0 = (tile / p.tiles_x) * kRows;
   const int d0 = slab * p.Ds;
@@ -396,6 +403,7 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) wx[q] = gx[i * KSF + ks + k8 + q];
         vec8 ahi[R], alo[R];
+        bool nz = false;
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const float* gyr = gy + (wave * R + t) * KSF + ks + k8;
@@ -403,11 +411,15 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
           for (int q = 0; q < 8; ++q) {
             const float w =
                 WEND ? wendland_c2(wx[q] + gyr[q]) * WeightGain<T>::value : wx[q] * gyr[q];
+            nz = nz || w != 0.0f;
             const T hw = (T)w;
             ahi[t][q] = hw;
             alo[t][q] = (T)(w - (float)hw);
           }
         }
+        // compact support: a k-step in which no pair of this wave's nodes
+        // has weight adds nothing; its matrix instructions are skipped
+        if (WEND && !__any(nz)) continue;
 #pragma unroll
         for (int q = 0; q < NTS; ++q) {
 #pragma unroll
@@ -949,7 +961,7 @@ hipError_t launch_lp_impl(LPParams p, hipStream_t s) {
                         : (const void*)fit_lp_kernel<DEG, NTS, S, T, false, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int64_t blocks = (int64_t)p.tiles * p.nslab;
+  const int64_t blocks = (int64_t)(WEND ? p.slots : p.tiles) * p.nslab;
   if (WEND)
     hipLaunchKernelGGL((fit_lp_kernel<DEG, NTS, S, T, true, true>), dim3((unsigned)blocks),
                        dim3(kThreads), lds, s, p);
@@ -1107,7 +1119,7 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
   }
   int nts, ds, nslab;
   lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
-  LPParams p;
+  LPParams p{};
   p.pts = a.pts;
   p.vals_t = vals_t;
   p.shift = shift;
@@ -1143,6 +1155,7 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
     p.pts = cells->pts_s;
     p.vals_t = cells->vals_ts;
     p.torder = cells->torder;
+    p.slots = (int)tile_order_slots(p.tiles_x, p.tiles / p.tiles_x);
     p.tile_start = cells->tile_start;
     p.tile_list = cells->tile_list;
     return fp16 ? launch_lp_terms<_Float16, true>(p, a.degree, nts, terms, stream)

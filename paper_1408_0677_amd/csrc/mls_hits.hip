@@ -73,7 +73,7 @@ hipError_t launch_hits(const HitArgs& a, hipStream_t s) {
                      a.dy, a.W, a.H, a.keys, a.idx);
   int bits = 8;
   while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)none) ++bits;
-  hipError_t e = radix_sort_pairs(a.keys, a.idx, a.keys2, a.idx2, a.n, bits, a.hist, s);
+  hipError_t e = radix_sort_pairs(a.keys, a.idx, a.keys2, a.idx2, a.n, bits, a.hist, a.ssum, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(hit_mean_kernel, dim3(gb), dim3(256), 0, s, a.keys, a.idx, a.n, none, a.vals,
                      a.D, (int64_t)a.W * a.H, a.fields, a.deg_out, a.grads);

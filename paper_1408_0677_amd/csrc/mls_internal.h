@@ -109,7 +109,7 @@ struct CellArgs {
   uint32_t* perm;          // [n] input index of each sorted point
   float* pts_s;            // [n][2] in cell order
   float* vals_ts;          // [D][n] in cell order
-  uint32_t* torder;        // [tiles] node tiles by descending work
+  uint32_t* torder;        // [tile_order_slots] node tile of each workgroup slot
   // per-tile point lists: the cell-ordered indices of the points within h
   // of some node of the tile (in cell order), tile t's entries at
   // [tile_start[t], tile_start[t + 1]) of tile_list
@@ -125,12 +125,19 @@ struct CellArgs {
   uint32_t* tkeys2;        // [tiles]
   uint32_t* torder2;       // [tiles]
   uint32_t* thist;         // [256 * radix_blocks(tiles)]
+  uint32_t* sorder;        // [tiles] supertiles by descending work
+  uint32_t* ssum;          // [scan_sums_words(largest scan)] scan block sums
 };
 int64_t radix_blocks(int64_t n);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits; the
-// result ends in (k0, v0); (k1, v1) and hist[256 * radix_blocks(n)] are scratch.
+// result ends in (k0, v0); (k1, v1), hist[256 * radix_blocks(n)] and
+// sums[scan_sums_words(256 * radix_blocks(n))] are scratch.
 hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                            int bits, uint32_t* hist, hipStream_t s);
+                            int bits, uint32_t* hist, uint32_t* sums, hipStream_t s);
+// Exclusive scan of `count` uint32 values in place (block sums in `sums`,
+// scan_sums_words(count) words).
+int64_t scan_sums_words(int64_t count);
+hipError_t scan_u32(uint32_t* v, int64_t count, uint32_t* sums, hipStream_t s);
 
 // Exact hits of the inverse-distance weight: nodes on data points take the
 // mean of those points' values and degree code 254.
@@ -145,6 +152,7 @@ struct HitArgs {
   uint8_t* deg_out;        // [H][W] or null
   float* grads;            // [D][2][H][W] or null (NaN at hit nodes)
   uint32_t *keys, *keys2, *idx, *idx2, *hist;   // scratch (n, n, n, n, 256 radix_blocks(n))
+  uint32_t* ssum;                               // scratch (scan block sums)
 };
 hipError_t launch_hits(const HitArgs& a, hipStream_t s);
 hipError_t launch_cells(const CellArgs& a, hipStream_t stream);
@@ -154,7 +162,8 @@ struct FitPlan {
   size_t o_pmin, o_pmax, o_shift, o_scale, o_vals;
   size_t o_keys, o_keys2, o_perm, o_perm2, o_hist, o_cs, o_pts, o_vals_s;
   size_t o_tk, o_tk2, o_to, o_to2, o_th;
-  size_t o_ts, o_tl;
+  size_t o_ts, o_tl, o_so, o_ssum;
+  int64_t order_slots;
   int64_t list_cap;       // entries of the per-tile point lists, at most
   size_t total;
   int ncx, ncy, tiles_x, tiles;
@@ -175,6 +184,18 @@ struct LPCells {
   int ncx, ncy;
   CellGeom geom;
 };
+
+// Workgroup slots of the compact-support fit's tile order: node tiles are
+// grouped into 4 x 4 supertiles, and the supertiles (heaviest first) are
+// dealt to the eight XCDs in turn, each supertile's 16 tiles on 16
+// consecutive slots of one XCD, so that tiles sharing points share an L2.
+// Slots without a tile hold 0xFFFFFFFF.
+constexpr int kSuperTile = 4;
+inline int64_t tile_order_slots(int tiles_x, int tiles_y) {
+  const int64_t sx = (tiles_x + kSuperTile - 1) / kSuperTile;
+  const int64_t sy = (tiles_y + kSuperTile - 1) / kSuperTile;
+  return 8 * kSuperTile * kSuperTile * ((sx * sy + 7) / 8);
+}
 
 // Upper bound of the per-tile point list entries: a point lies within h of
 // the node rectangles of at most this many tiles.

@@ -51,16 +51,32 @@ __global__ __launch_bounds__(256) void attr_range_kernel(const float* vals, int6
   }
 }
 
+// One block per attribute: min / max over the partial ranges (min and max
+// are exact, so the order of the reduction does not matter).
 __global__ __launch_bounds__(256) void attr_finalize_kernel(const float* pmin, const float* pmax,
                                                             int nblk, int D, float* shift,
                                                             float* scale) {
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= D) return;
+  __shared__ float slo[4], shi[4];
+  const int d = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   float lo = INFINITY, hi = -INFINITY;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = t; b < nblk; b += 256) {
     lo = fminf(lo, pmin[(int64_t)b * D + d]);
     hi = fmaxf(hi, pmax[(int64_t)b * D + d]);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+  }
+  if (lane == 0) {
+    slo[wave] = lo;
+    shi[wave] = hi;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  lo = fminf(fminf(slo[0], slo[1]), fminf(slo[2], slo[3]));
+  hi = fmaxf(fmaxf(shi[0], shi[1]), fmaxf(shi[2], shi[3]));
   // float64 midpoint and half-range, rounded once
   const double mid = 0.5 * ((double)lo + (double)hi);
   const double half = 0.5 * ((double)hi - (double)lo);
@@ -101,8 +117,8 @@ hipError_t launch_stage(const float* vals, int64_t n, int D, float* pmin, float*
   const int dblk = (D + 31) / 32;
   hipLaunchKernelGGL(attr_range_kernel, dim3((unsigned)nblk, dblk), dim3(32, 8), 0, s, vals, n,
                      D, pmin, pmax);
-  hipLaunchKernelGGL(attr_finalize_kernel, dim3((D + 255) / 256), dim3(256), 0, s, pmin, pmax,
-                     (int)nblk, D, shift, scale);
+  hipLaunchKernelGGL(attr_finalize_kernel, dim3(D), dim3(256), 0, s, pmin, pmax, (int)nblk, D,
+                     shift, scale);
   hipLaunchKernelGGL(stage_values_kernel, dim3((unsigned)((n + 31) / 32), dblk), dim3(32, 8), 0,
                      s, vals, n, D, shift, scale, vals_t);
   return hipGetLastError();
