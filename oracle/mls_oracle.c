@@ -761,3 +761,97 @@ int64_t oracle_contour_f32(const float* field, int32_t H, int32_t W, double x0,
   free(lv);
   return r;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Space mappings of the fields (Sec. 3.4, Fig. 5b-d)                      */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Discrete colours (Fig. 5b): each region between isovalues takes one
+ * colour, so a node's colour is decided by its band, the number of
+ * isovalues at or below its value (the same "at or above counts as above"
+ * tie rule as the contour cases).  NaN values get band 255.  The isovalues
+ * need not be sorted.  fields[D][P], iso[D][n_iso], bands[D][P].
+ */
+int oracle_map_bands(const float* fields, int32_t D, int64_t P, const float* iso,
+                     int32_t n_iso, uint8_t* bands) {
+  if (!fields || !bands || D < 1 || P < 0 || n_iso < 1 || n_iso > 254 || !iso) return -1;
+  for (int32_t d = 0; d < D; ++d) {
+    for (int64_t q = 0; q < P; ++q) {
+      float v = fields[(int64_t)d * P + q];
+      if (isnan(v)) {
+        bands[(int64_t)d * P + q] = 255;
+        continue;
+      }
+      int b = 0;
+      for (int32_t k = 0; k < n_iso; ++k)
+        if (v >= iso[(int64_t)d * n_iso + k]) ++b;
+      bands[(int64_t)d * P + q] = (uint8_t)b;
+    }
+  }
+  return 0;
+}
+
+/*
+ * Adaptive contour lines (Fig. 5d): the gradient of the field sets the
+ * local spacing of the lines on screen, finer lines fade in where that
+ * spacing is wide (space expanded) and out where it is narrow (space
+ * compressed).  Reading (the paper gives no formula):
+ *   - level j = 0 .. n_levels-1 has lines at origin + k spacing / 2^j;
+ *   - at a node with value f and gradient g = (g_x, g_y) the field changes
+ *     by r = |(g_x dx, g_y dy)| per pixel along its steepest pixel
+ *     direction (the gradient in pixel coordinates), and level j's lines
+ *     are s_j = (spacing / 2^j) / r pixels apart;
+ *   - level 0 is always drawn; level j >= 1 with opacity
+ *     a_j = clamp((s_j - fade_lo) / (fade_hi - fade_lo), 0, 1);
+ *   - the distance in pixels to the nearest level-j line is
+ *     e_j = |t - round(t)| s_j with t = (f - origin) / (spacing / 2^j);
+ *   - the line intensity is max_j a_j max(0, 1 - e_j / halfwidth), in
+ *     [0, 1]; NaN where f is NaN, 0 where r is 0 or not finite.
+ * fields[D][P], grads[D][2][P] (d/dx, d/dy), levels[D][2] (origin,
+ * spacing), out[D][P].
+ */
+int oracle_map_adaptive(const float* fields, const float* grads, int32_t D, int64_t P,
+                        const float* levels, double dx, double dy, int32_t n_levels,
+                        double halfwidth, double fade_lo, double fade_hi, double* out) {
+  if (!fields || !grads || !levels || !out || D < 1 || P < 0 || n_levels < 1 ||
+      n_levels > 30 || !(halfwidth > 0.0) || !(fade_hi > fade_lo))
+    return -1;
+  for (int32_t d = 0; d < D; ++d) {
+    double origin = (double)levels[2 * d], spacing = (double)levels[2 * d + 1];
+    for (int64_t q = 0; q < P; ++q) {
+      double f = (double)fields[(int64_t)d * P + q];
+      double gx = (double)grads[((int64_t)2 * d) * P + q];
+      double gy = (double)grads[((int64_t)2 * d + 1) * P + q];
+      double* o = out + (int64_t)d * P + q;
+      if (isnan(f)) {
+        *o = NAN;
+        continue;
+      }
+      double px = gx * dx, py = gy * dy;
+      double per_px = sqrt(px * px + py * py);
+      if (!(per_px > 0.0) || !isfinite(per_px) || !(spacing > 0.0)) {
+        *o = 0.0;
+        continue;
+      }
+      double best = 0.0;
+      for (int32_t j = 0; j < n_levels; ++j) {
+        double step = spacing / ldexp(1.0, j);
+        double s = step / per_px;
+        double a = 1.0;
+        if (j > 0) {
+          a = (s - fade_lo) / (fade_hi - fade_lo);
+          if (a < 0.0) a = 0.0;
+          if (a > 1.0) a = 1.0;
+        }
+        double t = (f - origin) / step;
+        double e = fabs(t - round(t)) * s;
+        double line = 1.0 - e / halfwidth;
+        if (line < 0.0) line = 0.0;
+        if (a * line > best) best = a * line;
+      }
+      *o = best;
+    }
+  }
+  return 0;
+}

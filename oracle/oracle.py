@@ -72,6 +72,10 @@ def _load():
     lib.oracle_layout_step_nodes.argtypes = [P, i64, P, P, P, P, f64, f64, f64, f64, P, i64,
                                              i32, P]
     lib.oracle_layout_step_nodes.restype = ctypes.c_int
+    lib.oracle_map_bands.argtypes = [P, i32, i64, P, i32, P]
+    lib.oracle_map_bands.restype = ctypes.c_int
+    lib.oracle_map_adaptive.argtypes = [P, P, i32, i64, P, f64, f64, i32, f64, f64, f64, P]
+    lib.oracle_map_adaptive.restype = ctypes.c_int
     for name in ("oracle_contour_f64", "oracle_contour_f32"):
         fn = getattr(lib, name)
         fn.argtypes = [P, i32, i32, f64, f64, f64, f64, P, i32, i32, P, P, P, i64]
@@ -254,3 +258,37 @@ def contour(fields, grid, iso, f32=False):
         segs_all.append(segs[:cnt])
         ids_all.append(ids[:cnt])
     return cases, np.concatenate(segs_all), np.concatenate(ids_all)
+
+
+def map_bands(fields, iso):
+    """Discrete-colour bands (Sec. 3.4, Fig. 5b) of float32 fields (D, ...)
+    at isovalues (D, n_iso): per value the number of isovalues at or below
+    it, 255 for NaN.  Returns uint8 of the fields' shape."""
+    f = np.ascontiguousarray(fields, dtype=np.float32)
+    D = f.shape[0]
+    lv = np.ascontiguousarray(np.asarray(iso, dtype=np.float32).reshape(D, -1))
+    out = np.empty(f.shape, np.uint8)
+    P = f.size // D
+    rc = _load().oracle_map_bands(_ptr(f), D, P, _ptr(lv), lv.shape[1], _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_map_bands rejected its arguments")
+    return out
+
+
+def map_adaptive(fields, grads, levels, grid, n_levels=3, halfwidth=1.0, fade_lo=4.0,
+                 fade_hi=12.0):
+    """Adaptive contour-line intensity (Sec. 3.4, Fig. 5d) of float32 fields
+    (D, H, W) with gradients (D, 2, H, W) and levels (D, 2) = (origin,
+    spacing) per field.  Returns float64 (D, H, W)."""
+    f = np.ascontiguousarray(fields, dtype=np.float32)
+    D = f.shape[0]
+    g = np.ascontiguousarray(grads, dtype=np.float32)
+    lv = np.ascontiguousarray(np.asarray(levels, dtype=np.float32).reshape(D, 2))
+    out = np.empty(f.shape, np.float64)
+    P = f.size // D
+    rc = _load().oracle_map_adaptive(_ptr(f), _ptr(g), D, P, _ptr(lv), float(grid["dx"]),
+                                     float(grid["dy"]), int(n_levels), float(halfwidth),
+                                     float(fade_lo), float(fade_hi), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_map_adaptive rejected its arguments")
+    return out

@@ -60,11 +60,21 @@ MUTATIONS = [
      "const double s = C / (rx * rx + ry * ry + eta);"),
     ("sampled layout step offsets the wrong node", "pos_out[2 * i] = pos_in[2 * v] + mv[0];",
      "pos_out[2 * i] = pos_in[2 * i] + mv[0];"),
+    ("band tie counts below", "if (v >= iso[(int64_t)d * n_iso + k]) ++b;",
+     "if (v > iso[(int64_t)d * n_iso + k]) ++b;"),
+    ("adaptive level 0 fades too", "        if (j > 0) {\n          a = (s - fade_lo)",
+     "        if (j >= 0) {\n          a = (s - fade_lo)"),
+    ("adaptive levels coarsen", "double step = spacing / ldexp(1.0, j);",
+     "double step = spacing * ldexp(1.0, j);"),
+    ("adaptive pixel size of the wrong axis", "double px = gx * dx, py = gy * dy;",
+     "double px = gx * dy, py = gy * dy;"),
+    ("adaptive distance in steps, not pixels", "double e = fabs(t - round(t)) * s;",
+     "double e = fabs(t - round(t));"),
 ]
 
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_contour_pins.py",
              "tests/test_oracle_grad_pins.py", "tests/test_oracle_rigid_pins.py",
-             "tests/test_oracle_layout_pins.py"]
+             "tests/test_oracle_layout_pins.py", "tests/test_oracle_map_pins.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
