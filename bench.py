@@ -302,6 +302,57 @@ def layout_bench(args):
     return out
 
 
+def maps_bench(args):
+    """The space mappings of Sec. 3.4 on the 1024^2 / 13-field fit: discrete
+    bands with colours, and adaptive contour lines from the fit's
+    gradients; HBM bound (algorithmic bytes: bands 4 B read + 5 B written
+    per node and field; lines 12 B read + 4 B written)."""
+    import torch
+    from paper_1408_0677_amd import api, workloads as wl
+    w = wl.c2()
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(w.points).to(dev)
+    V = torch.from_numpy(w.values).to(dev)
+    F, G, _ = api.fit_grad(P, V, w.grid, basis=w.basis, h=w.h)
+    iso = torch.from_numpy(w.iso()).to(dev)
+    cmap = torch.arange(w.d * (w.n_iso + 1), dtype=torch.int32, device=dev)
+    lo, hi = w.values.min(0), w.values.max(0)
+    levels = torch.from_numpy(np.stack([lo, (hi - lo) / 11.0], 1).astype(np.float32)).to(dev)
+    ctx = api.default_context(0)
+    stream = torch.cuda.current_stream()
+    nodes = w.grid["width"] * w.grid["height"] * w.d
+    res = {}
+    for name, fn, nbytes in (
+            ("bands", lambda: api.map_bands(F, w.grid, iso, colormap=cmap, ctx=ctx), 9 * nodes),
+            ("lines", lambda: api.map_adaptive(F, G, w.grid, levels, ctx=ctx), 16 * nodes)):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        ctx.trace(True)
+        ms = []
+        for _ in range(max(args.steps, 10)):
+            fn()
+            ms.append(list(ctx.trace_last()["stages"].values())[0])
+        ctx.trace(False)
+        k = float(np.mean(ms))
+        res[name] = {"kernel_ms": k, "algorithmic_bytes": nbytes,
+                     "achieved_GBs": nbytes / (k * 1e-3) / 1e9}
+    lines = res["lines"]
+    return {
+        "metric": "space mappings (Sec. 3.4): fields/s at 1024^2, bands + colours and adaptive "
+                  "lines",
+        "value": w.d / ((res["bands"]["kernel_ms"] + lines["kernel_ms"]) * 1e-3),
+        "unit": "fields/s", "n_gpus": 1, "steps": max(args.steps, 10),
+        "warmup": max(args.warmup, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 in, f64 lines", "data": "synthetic",
+        "config": {"workload": "c2_maps_13_fields_1024", "fields": w.d, "isovalues": w.n_iso,
+                   "adaptive_levels": 3},
+        "per_mapping": res,
+        "roofline": {"bound": "hbm", "achieved": lines["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": lines["achieved_GBs"] / PEAK_HBM_GBS,
+                     "traffic": None, "kernel": "map_adaptive_kernel"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,7 +364,7 @@ def main():
                     help="single fits behind the p50/p99 fit latency (default: 100, "
                          "fewer where 100 would take over 20 s)")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c4", "c5", "t1", "layout"],
+                    choices=["c2", "c3", "c4", "c5", "t1", "layout", "maps"],
                     help="c2: the 1024^2 float64 fit + contour step (default); c3: the "
                          "2048^2 / D = 64 quadratic bfloat16 fit; c5: the 4096^2 / "
                          "N = 10^6 Wendland bfloat16 fit + contour; c4: the served "
@@ -321,7 +372,8 @@ def main():
                          "shape (600^2, N = 306 / 1000 / 2245, D = 2, linear, the "
                          "inverse-distance weight of Eq. 4), float64; layout: the "
                          "planarity-preserving layout of Sec. 3.2 at the timing-table "
-                         "sizes, float64")
+                         "sizes, float64; maps: the discrete-colour and adaptive-line "
+                         "mappings of Sec. 3.4 of the 1024^2 / 13-field fit")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -340,6 +392,10 @@ def main():
 
     if args.workload == "layout":
         print(json.dumps(layout_bench(args)), flush=True)
+        return
+
+    if args.workload == "maps":
+        print(json.dumps(maps_bench(args)), flush=True)
         return
 
     if args.workload == "t1":

@@ -366,6 +366,56 @@ mls_status mls_contour_static(mls_context* ctx, const float* d_fields, int32_t d
                               uint8_t* d_cases, float* d_segments, int32_t* d_seg_ids,
                               int64_t capacity, int64_t* d_count, void* stream);
 
+/*
+ * Discrete colours (Sec. 3.4, Fig. 5b): per node, the band of its value --
+ * the number of isovalues at or below it, the same tie rule as the contour
+ * cases -- and optionally the band's colour.
+ *  d_fields   float32 [d][height][width], device
+ *  d_iso      float32 [d][n_iso], device (any order), 1 <= n_iso <= 254
+ *  d_colormap uint32 [d][n_iso + 1] RGBA8 colour of each band, device, or
+ *             NULL when d_rgba is NULL
+ *  d_bands    uint8 [d][height][width] output (255 where the value is
+ *             NaN), device, or NULL
+ *  d_rgba     uint32 [d][height][width] output (0 where NaN), device, or
+ *             NULL; at least one of d_bands, d_rgba
+ * Enqueued on the stream; no scratch.
+ */
+mls_status mls_map_bands(mls_context* ctx, const float* d_fields, int32_t d,
+                         const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                         const uint32_t* d_colormap, uint8_t* d_bands, uint32_t* d_rgba,
+                         void* stream);
+
+/* Adaptive contour lines (Sec. 3.4, Fig. 5d): lines fade in where space is
+ * expanded (the field changes slowly per pixel) and out where it is
+ * compressed.  Level j = 0 .. levels-1 has lines at origin + k spacing/2^j;
+ * at a node with gradient g the field changes by r = |(g_x dx, g_y dy)|
+ * per pixel, so level j's lines are s_j = (spacing / 2^j) / r pixels
+ * apart.  Level 0 is always drawn; level j >= 1 with opacity
+ * clamp((s_j - fade_lo) / (fade_hi - fade_lo), 0, 1).  The intensity is the
+ * largest opacity x max(0, 1 - e_j / halfwidth) over the levels, e_j the
+ * pixel distance to the nearest level-j line: in [0, 1], NaN where the
+ * value is NaN, 0 where r is 0 or not finite. */
+typedef struct {
+  int32_t levels;     /* 1 .. 30 */
+  double halfwidth;   /* line half-width in pixels, finite, > 0 */
+  double fade_lo;     /* finite, fade_lo < fade_hi */
+  double fade_hi;
+} mls_adaptive_params;
+
+/*
+ *  d_fields    float32 [d][height][width], device
+ *  d_grad      float32 [d][2][height][width] (d/dx, d/dy, as mls_fit_grad
+ *              writes them), device
+ *  d_levels    float32 [d][2] (origin, spacing of the level-0 lines),
+ *              device
+ *  d_intensity float32 [d][height][width] output, device
+ * Enqueued on the stream; no scratch.
+ */
+mls_status mls_map_adaptive(mls_context* ctx, const float* d_fields, const float* d_grad,
+                            int32_t d, const mls_grid* grid, const float* d_levels,
+                            const mls_adaptive_params* params, float* d_intensity,
+                            void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Served form: resident point sets and continuously batched fit requests    */
 /* ------------------------------------------------------------------------ */

@@ -21,7 +21,8 @@ EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_server_put_points", "mls_server_release_points", "mls_server_submit",
            "mls_server_poll", "mls_server_wait", "mls_server_last_error",
            "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad", "mls_layout",
-           "mls_contour_static", "mls_context_trace", "mls_context_trace_last")
+           "mls_contour_static", "mls_context_trace", "mls_context_trace_last",
+           "mls_map_bands", "mls_map_adaptive")
 
 
 class MlsGrid(ctypes.Structure):
@@ -44,6 +45,11 @@ class MlsSolveOpts(ctypes.Structure):
 class MlsLayoutParams(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double), ("D", ctypes.c_double), ("eta", ctypes.c_double),
                 ("t0", ctypes.c_double), ("lam", ctypes.c_double)]
+
+
+class MlsAdaptiveParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("halfwidth", ctypes.c_double),
+                ("fade_lo", ctypes.c_double), ("fade_hi", ctypes.c_double)]
 
 
 class MlsRequest(ctypes.Structure):
@@ -111,6 +117,11 @@ def load():
     lib.mls_fit_scratch_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(MlsWeight),
                                           ctypes.POINTER(MlsGrid)]
     lib.mls_fit_scratch_bytes.restype = ctypes.c_size_t
+    lib.mls_map_bands.argtypes = [P, P, i32, ctypes.POINTER(MlsGrid), P, i32, P, P, P, P]
+    lib.mls_map_bands.restype = ctypes.c_int
+    lib.mls_map_adaptive.argtypes = [P, P, P, i32, ctypes.POINTER(MlsGrid), P,
+                                     ctypes.POINTER(MlsAdaptiveParams), P, P]
+    lib.mls_map_adaptive.restype = ctypes.c_int
     lib.mls_context_trace.argtypes = [P, i32, ctypes.c_char_p]
     lib.mls_context_trace.restype = ctypes.c_int
     lib.mls_context_trace_last.argtypes = [P, ctypes.POINTER(MlsTraceRecord)]

@@ -286,6 +286,65 @@ def contour(fields, grid: dict, iso, want_cases: bool = True, want_ids: bool = T
     return segs[:n], (ids[:n] if ids is not None else None), cases
 
 
+def map_bands(fields, grid: dict, iso, colormap=None, want_bands: bool = True,
+              ctx: Context | None = None, stream=None):
+    """Discrete-colour bands (Sec. 3.4, Fig. 5b) of ``fields`` (D, H, W) at
+    isovalues ``iso`` (D, n_iso), both float32 device tensors: returns
+    ``(bands uint8 (D, H, W) or None, rgba (D, H, W) or None)``; ``colormap``
+    (D, n_iso + 1) int32 device tensor of RGBA8 words, one per band."""
+    import torch
+    _require(fields, "fields", torch.float32)
+    if fields.dim() == 2:
+        fields = fields.unsqueeze(0)
+    D, H, W = fields.shape
+    if (W, H) != (int(grid["width"]), int(grid["height"])):
+        raise ValueError(f"fields are {H} x {W}, the grid {grid['height']} x {grid['width']}")
+    dev = fields.device
+    _require(iso, "iso", torch.float32, device=dev)
+    if iso.numel() % D or iso.numel() == 0:
+        raise ValueError("iso must hold n_iso values per field")
+    n_iso = iso.numel() // D
+    if colormap is not None:
+        # RGBA8 colours packed into 32-bit words (held as int32 tensors)
+        _require(colormap, "colormap", torch.int32, device=dev, numel=D * (n_iso + 1))
+    bands = torch.empty((D, H, W), dtype=torch.uint8, device=dev) if want_bands else None
+    rgba = (torch.empty((D, H, W), dtype=colormap.dtype, device=dev)
+            if colormap is not None else None)
+    ctx = ctx or default_context(dev.index)
+    st = _lib.load().mls_map_bands(ctx.handle, _ptr(fields), D, ctypes.byref(grid_struct(grid)),
+                                   _ptr(iso), n_iso, _ptr(colormap), _ptr(bands), _ptr(rgba),
+                                   _stream_handle(stream))
+    _check(st, "mls_map_bands")
+    return bands, rgba
+
+
+def map_adaptive(fields, grads, grid: dict, levels, n_levels: int = 3, halfwidth: float = 1.0,
+                 fade_lo: float = 4.0, fade_hi: float = 12.0, ctx: Context | None = None,
+                 stream=None):
+    """Adaptive contour-line intensity (Sec. 3.4, Fig. 5d) of ``fields``
+    (D, H, W) with their gradients ``grads`` (D, 2, H, W) (as fit_grad
+    returns them) and ``levels`` (D, 2) = (origin, spacing) of the level-0
+    lines, float32 device tensors.  Returns float32 (D, H, W)."""
+    import torch
+    _require(fields, "fields", torch.float32)
+    if fields.dim() == 2:
+        fields = fields.unsqueeze(0)
+    D, H, W = fields.shape
+    if (W, H) != (int(grid["width"]), int(grid["height"])):
+        raise ValueError(f"fields are {H} x {W}, the grid {grid['height']} x {grid['width']}")
+    dev = fields.device
+    _require(grads, "grads", torch.float32, device=dev, numel=2 * D * H * W)
+    _require(levels, "levels", torch.float32, device=dev, numel=2 * D)
+    out = torch.empty((D, H, W), dtype=torch.float32, device=dev)
+    prm = _lib.MlsAdaptiveParams(int(n_levels), float(halfwidth), float(fade_lo), float(fade_hi))
+    ctx = ctx or default_context(dev.index)
+    st = _lib.load().mls_map_adaptive(ctx.handle, _ptr(fields), _ptr(grads), D,
+                                      ctypes.byref(grid_struct(grid)), _ptr(levels),
+                                      ctypes.byref(prm), _ptr(out), _stream_handle(stream))
+    _check(st, "mls_map_adaptive")
+    return out
+
+
 def contour_static(fields, grid: dict, iso, segments, count, ids=None, cases=None,
                    ctx: Context | None = None, stream=None):
     """Allocation-free marching squares (mls_contour_static) into caller

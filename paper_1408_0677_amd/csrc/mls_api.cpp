@@ -728,6 +728,110 @@ mls_status mls_layout(mls_context* ctx, float* d_pos, int64_t n, const int32_t* 
   return scratch_release(ctx, s);
 }
 
+// Grid checks shared by the mappings.
+static mls_status map_grid_check(const mls_grid* grid, int32_t d) {
+  if (d < 1) return fail(MLS_ERR_INVALID_ARG, "d = %d; need at least one field", d);
+  if (!grid) return fail(MLS_ERR_INVALID_ARG, "grid is NULL");
+  if (grid->width < 1 || grid->height < 1)
+    return fail(MLS_ERR_INVALID_ARG, "grid %d x %d; need width, height >= 1", grid->width,
+                grid->height);
+  if (!is_finite(grid->dx) || !is_finite(grid->dy))
+    return fail(MLS_ERR_INVALID_ARG, "grid spacing must be finite");
+  return MLS_OK;
+}
+
+mls_status mls_map_bands(mls_context* ctx, const float* d_fields, int32_t d,
+                         const mls_grid* grid, const float* d_iso, int32_t n_iso,
+                         const uint32_t* d_colormap, uint8_t* d_bands, uint32_t* d_rgba,
+                         void* stream) {
+  g_last_error[0] = '\0';
+  mls_status st = map_grid_check(grid, d);
+  if (st != MLS_OK) return st;
+  if (n_iso < 1 || n_iso > 254)
+    return fail(MLS_ERR_INVALID_ARG, "n_iso = %d; need 1 .. 254", n_iso);
+  if (!d_fields) return fail(MLS_ERR_INVALID_ARG, "d_fields is NULL");
+  if (!d_iso) return fail(MLS_ERR_INVALID_ARG, "d_iso is NULL");
+  if (!d_bands && !d_rgba) return fail(MLS_ERR_INVALID_ARG, "d_bands and d_rgba are both NULL");
+  if (d_rgba && !d_colormap) return fail(MLS_ERR_INVALID_ARG, "d_rgba needs d_colormap");
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  if ((st = check_device_ptr(ctx, d_fields, "d_fields")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_iso, "d_iso")) != MLS_OK) return st;
+  if (d_colormap && (st = check_device_ptr(ctx, d_colormap, "d_colormap")) != MLS_OK) return st;
+  if (d_bands && (st = check_device_ptr(ctx, d_bands, "d_bands")) != MLS_OK) return st;
+  if (d_rgba && (st = check_device_ptr(ctx, d_rgba, "d_rgba")) != MLS_OK) return st;
+  mls::MapBandsArgs a;
+  a.fields = d_fields;
+  a.iso = d_iso;
+  a.colormap = d_colormap;
+  a.D = d;
+  a.n_iso = n_iso;
+  a.P = (int64_t)grid->width * grid->height;
+  a.bands = d_bands;
+  a.rgba = d_rgba;
+  hipStream_t s = (hipStream_t)stream;
+  char meta[128];
+  std::snprintf(meta, sizeof(meta), "\"d\": %d, \"n_iso\": %d, \"width\": %d, \"height\": %d, ",
+                d, n_iso, grid->width, grid->height);
+  Tracer tr(ctx, s, "map_bands", meta);
+  e = mls::launch_map_bands(a, s);
+  if (e != hipSuccess) return device_fail(e, "band kernel launch");
+  tr.mark("bands");
+  tr.finish();
+  return MLS_OK;
+}
+
+mls_status mls_map_adaptive(mls_context* ctx, const float* d_fields, const float* d_grad,
+                            int32_t d, const mls_grid* grid, const float* d_levels,
+                            const mls_adaptive_params* params, float* d_intensity,
+                            void* stream) {
+  g_last_error[0] = '\0';
+  mls_status st = map_grid_check(grid, d);
+  if (st != MLS_OK) return st;
+  if (!params) return fail(MLS_ERR_INVALID_ARG, "params is NULL");
+  if (params->levels < 1 || params->levels > 30)
+    return fail(MLS_ERR_INVALID_ARG, "levels = %d; need 1 .. 30", params->levels);
+  if (!is_finite(params->halfwidth) || !(params->halfwidth > 0.0))
+    return fail(MLS_ERR_INVALID_ARG, "halfwidth = %g; need a finite value > 0", params->halfwidth);
+  if (!is_finite(params->fade_lo) || !is_finite(params->fade_hi) ||
+      !(params->fade_hi > params->fade_lo))
+    return fail(MLS_ERR_INVALID_ARG, "fade_lo = %g, fade_hi = %g; need finite fade_lo < fade_hi",
+                params->fade_lo, params->fade_hi);
+  if (!d_fields || !d_grad || !d_levels || !d_intensity)
+    return fail(MLS_ERR_INVALID_ARG, "a required device array is NULL");
+  if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_fail(e, "hipSetDevice");
+  if ((st = check_device_ptr(ctx, d_fields, "d_fields")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_grad, "d_grad")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_levels, "d_levels")) != MLS_OK) return st;
+  if ((st = check_device_ptr(ctx, d_intensity, "d_intensity")) != MLS_OK) return st;
+  mls::MapAdaptiveArgs a;
+  a.fields = d_fields;
+  a.grads = d_grad;
+  a.levels = d_levels;
+  a.D = d;
+  a.n_levels = params->levels;
+  a.P = (int64_t)grid->width * grid->height;
+  a.dx = grid->dx;
+  a.dy = grid->dy;
+  a.halfwidth = params->halfwidth;
+  a.fade_lo = params->fade_lo;
+  a.fade_hi = params->fade_hi;
+  a.out = d_intensity;
+  hipStream_t s = (hipStream_t)stream;
+  char meta[128];
+  std::snprintf(meta, sizeof(meta), "\"d\": %d, \"levels\": %d, \"width\": %d, \"height\": %d, ",
+                d, params->levels, grid->width, grid->height);
+  Tracer tr(ctx, s, "map_adaptive", meta);
+  e = mls::launch_map_adaptive(a, s);
+  if (e != hipSuccess) return device_fail(e, "adaptive line kernel launch");
+  tr.mark("lines");
+  tr.finish();
+  return MLS_OK;
+}
+
 mls_status mls_context_trace(mls_context* ctx, int32_t enable, const char* jsonl_path) {
   g_last_error[0] = '\0';
   if (!ctx) return fail(MLS_ERR_INVALID_ARG, "ctx is NULL");

@@ -229,6 +229,30 @@ hipError_t launch_contour(const ContourArgs& a, hipStream_t stream);
 hipError_t contour_static_scratch_resolve(int device);
 void* contour_static_scratch(int device);
 
+// Space mappings (discrete colour bands, adaptive contour lines) of D
+// fields of P nodes each.
+struct MapBandsArgs {
+  const float* fields;      // [D][P]
+  const float* iso;         // [D][n_iso]
+  const uint32_t* colormap; // [D][n_iso + 1] or null
+  int32_t D, n_iso;
+  int64_t P;
+  uint8_t* bands;           // [D][P] or null
+  uint32_t* rgba;           // [D][P] or null (needs colormap)
+};
+hipError_t launch_map_bands(const MapBandsArgs& a, hipStream_t s);
+
+struct MapAdaptiveArgs {
+  const float* fields;      // [D][P]
+  const float* grads;       // [D][2][P]
+  const float* levels;      // [D][2] origin, spacing
+  int32_t D, n_levels;
+  int64_t P;
+  double dx, dy, halfwidth, fade_lo, fade_hi;
+  float* out;               // [D][P]
+};
+hipError_t launch_map_adaptive(const MapAdaptiveArgs& a, hipStream_t s);
+
 // Planarity-preserving layout iterations (float64 state in buf0/buf1,
 // each [n][2]); pos holds the float32 positions in and out.
 struct LayoutArgs {

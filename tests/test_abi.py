@@ -236,3 +236,26 @@ def test_trace_arguments_rejected(lib):
     assert lib.mls_context_trace(None, 1, None) == -1
     rec = _lib.MlsTraceRecord()
     assert lib.mls_context_trace_last(None, ctypes.byref(rec)) == -1
+
+
+def test_map_arguments_rejected_before_device(lib):
+    from paper_1408_0677_amd import _lib
+    g = _lib.MlsGrid(0.0, 0.0, 0.1, 0.1, 8, 8)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.mls_map_bands(None, fake, 1, ctypes.byref(g), fake, 0, None, fake, None,
+                             None) == -1
+    assert b"n_iso" in lib.mls_last_error()
+    assert lib.mls_map_bands(None, fake, 1, ctypes.byref(g), fake, 3, None, None, None,
+                             None) == -1
+    assert b"both NULL" in lib.mls_last_error()
+    assert lib.mls_map_bands(None, fake, 1, ctypes.byref(g), fake, 3, None, None, fake,
+                             None) == -1
+    assert b"colormap" in lib.mls_last_error()
+    prm = _lib.MlsAdaptiveParams(3, 1.0, 5.0, 5.0)
+    assert lib.mls_map_adaptive(None, fake, fake, 1, ctypes.byref(g), fake, ctypes.byref(prm),
+                                fake, None) == -1
+    assert b"fade_lo" in lib.mls_last_error()
+    prm = _lib.MlsAdaptiveParams(3, 1.0, 4.0, 12.0)
+    assert lib.mls_map_adaptive(None, fake, fake, 1, ctypes.byref(g), fake, ctypes.byref(prm),
+                                fake, None) == -1
+    assert b"ctx is NULL" in lib.mls_last_error()
