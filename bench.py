@@ -139,15 +139,19 @@ def serve_bench(args):
     """The served form on the request mix: closed-loop saturation for the
     16-bit served precision (with the library plan, then with the autotuner
     choosing slab widths per shape class) and the plain path, then Poisson
-    arrivals at 0.5, 0.8 and 1.0 times the saturation rate."""
+    arrivals at 0.5, 0.8 and 1.0 times the saturation rate.  16-bit
+    requests of one kernel class share persistent batch kernels."""
     import torch
     from paper_1408_0677_amd import api, workloads as wl
 
     reqs = wl.c4_requests(count=args.requests)
     dev = torch.device("cuda:0")
     budget = 2 << 30
-    slot_scratch = max(api.fit_scratch_bytes(r.n, r.d, r.grid, "fp16") for r in reqs) + (1 << 20)
-    srv = api.Server(0, budget + args.slots * slot_scratch, args.slots, slot_scratch)
+    # a slot stages a whole batch: room for about 16 of the largest requests
+    slot_scratch = 16 * max(api.fit_scratch_bytes(r.n, r.d, r.grid, "fp16") for r in reqs) + \
+        (1 << 20)
+    # points + slots + the tuner's context scratch and output buffer
+    srv = api.Server(0, budget + (args.slots + 2) * slot_scratch, args.slots, slot_scratch)
     pids = [srv.put_points(torch.from_numpy(r.points).to(dev),
                            torch.from_numpy(r.values).to(dev)) for r in reqs]
     pairs = [r.grid["width"] * r.grid["height"] * r.n for r in reqs]
@@ -188,8 +192,12 @@ def serve_bench(args):
     for label, prec, tune in (("fp16", "fp16", False), ("fp16_tuned", "fp16", True),
                               ("f64", "f64", False)):
         srv.tuning(tune)
-        run(prec)                                  # warm-up pass (tunes new shape classes)
+        run(prec)                                  # warm-up pass (queues new shape classes)
         if tune:
+            # the tuner thread times the classes beside the scheduler
+            t_end = time.time() + 120
+            while srv.tuning_pending() and time.time() < t_end:
+                time.sleep(0.01)
             n_classes = srv.tuned_classes()
         wall, lat = run(prec)
         rate = len(reqs) / wall

@@ -57,6 +57,7 @@ typedef enum {
   MLS_ERR_CAPACITY = -3,      /* output buffer too small (contour) */
   MLS_ERR_DEVICE = -4,        /* HIP runtime error, wrong device */
   MLS_ERR_OVER_BUDGET = -5,   /* (server) request or point set exceeds the budget */
+  MLS_ERR_CANCELLED = -6,     /* (server) request cancelled or past its timeout */
   MLS_ERR_UNSUPPORTED = -7,   /* valid request the library does not run */
   MLS_PENDING = 1             /* (server) request not finished yet */
 } mls_status;
@@ -422,13 +423,23 @@ mls_status mls_map_adaptive(mls_context* ctx, const float* d_fields, const float
 /*
  * The paper re-evaluates the MLS field on every interaction (Sec. 3.5,
  * Sec. 4.5).  A server keeps point sets resident on one device and runs fit
- * requests as they arrive: a scheduler thread admits queued requests in
- * arrival order onto `slots` execution slots (a stream and a context with
- * reserved scratch each), so requests overlap on the device and a request
- * that arrives while others run starts as soon as a slot is free.  Memory:
- * resident point sets + slots x slot_scratch_bytes <= hbm_budget_bytes;
- * admitted requests allocate nothing.  All server calls are thread-safe.
- * Results of a request are bit-identical whether it runs alone or among
+ * requests as they arrive, on `slots` execution slots (a stream and a
+ * context with reserved scratch each).  Whenever a slot is free, a
+ * scheduler thread gives it the request at the head of the queue together
+ * with the later queued requests of the same kernel class (16-bit one-pass
+ * fits with the Gaussian weight and no gradients, of one degree, feature
+ * tiles per workgroup, terms and format), in arrival order, while their
+ * staging fits the slot's scratch.  Such a batch runs as one persistent
+ * kernel whose workgroups take (request, tile) work items from a device
+ * counter; each request's completion flag lives in pinned host memory and
+ * is set by the workgroup that finishes the request's last item, so
+ * requests retire one by one while the batch runs on, and a request that
+ * arrives meanwhile joins the next batch a slot takes.  Other requests
+ * (MLS_PREC_F64, the Wendland weight, the two-pass bfloat16 form) run
+ * alone on a slot.  Memory: resident point sets + slots x slot_scratch_bytes
+ * (+ the tuner's reservation) <= hbm_budget_bytes; admitted requests
+ * allocate nothing.  All server calls are thread-safe.  Results of a request
+ * are bit-identical to mls_fit's with the same arguments, alone or among
  * others.  Timestamps are seconds since server creation (steady clock).
  */
 typedef struct mls_server mls_server;
@@ -442,16 +453,20 @@ typedef struct {
   mls_solve_opts opts;    /* zeros select nothing useful: set tau, floor */
   float* d_fields;        /* [d][height][width] output, caller-owned device */
   uint8_t* d_degree;      /* [height][width] output or NULL */
+  double timeout_s;       /* > 0: cancel the request this many seconds after
+                           * submit if it has not finished; 0: no timeout */
 } mls_request;
 
 typedef struct {
-  int32_t status;         /* MLS_PENDING, MLS_OK or the fit's error status */
+  int32_t status;         /* MLS_PENDING, MLS_OK, MLS_ERR_CANCELLED, or the
+                           * fit's error status */
   double t_submit, t_admit, t_start, t_end;
   char detail[128];       /* error detail */
 } mls_result;
 
 /* Create a server on `device` with `slots` execution slots (1..64) of
- * `slot_scratch_bytes` reserved scratch each (see mls_fit_scratch_bytes). */
+ * `slot_scratch_bytes` reserved scratch each (see mls_fit_scratch_bytes;
+ * a batch stages all its requests in one slot's scratch). */
 mls_status mls_server_create(int32_t device, size_t hbm_budget_bytes, int32_t slots,
                              size_t slot_scratch_bytes, mls_server** out);
 /* Wait for all submitted requests, then free everything. */
@@ -462,14 +477,24 @@ void mls_server_destroy(mls_server* srv);
  * first (the server's streams are not ordered with the caller's). */
 mls_status mls_server_put_points(mls_server* srv, const float* points, const float* values,
                                  int64_t n, int32_t d, uint64_t* pointset);
-/* Drop a point set once no queued or running request uses it. */
+/* Drop a point set once no queued or running request (or tuning run) uses
+ * it. */
 mls_status mls_server_release_points(mls_server* srv, uint64_t pointset);
-/* Queue a request (returns at once).  The request's output buffers are
- * written from a server stream that is not ordered with the caller's
- * streams: work the caller queued on them must be complete at submit.  MLS_ERR_OVER_BUDGET if its scratch
- * exceeds a slot's; argument errors of the fit itself surface in its
- * result. */
+/* Queue a request (returns at once).  Every check of mls_fit is made here:
+ * a request that mls_fit would refuse is refused with the same status.
+ * MLS_ERR_OVER_BUDGET if its scratch exceeds a slot's.  The request's
+ * output buffers are written from a server stream that is not ordered with
+ * the caller's streams: work the caller queued on them must be complete at
+ * submit, and they must not be read before the request has finished. */
 mls_status mls_server_submit(mls_server* srv, const mls_request* req, uint64_t* ticket);
+/* Cancel a queued or running request.  A queued request is dropped at once;
+ * a batched request's remaining work items are skipped (items already
+ * started finish), so its outputs are left partly written; a request
+ * running alone on a slot completes.  Its result status is
+ * MLS_ERR_CANCELLED, unless it had finished before the cancellation took
+ * effect (then MLS_OK).  MLS_ERR_INVALID_ARG for an unknown or finished
+ * ticket.  A request's timeout_s acts the same way. */
+mls_status mls_server_cancel(mls_server* srv, uint64_t ticket);
 /* MLS_PENDING while the request runs; MLS_OK once finished (the result is
  * written, the ticket retired; result.status holds the fit's status). */
 mls_status mls_server_poll(mls_server* srv, uint64_t ticket, mls_result* out);
@@ -480,18 +505,29 @@ const char* mls_server_last_error(void);
 
 /*
  * Autotuner of the served 16-bit fits (callers that serve many requests of
- * recurring shapes).  enable = 1: the first request of each shape class
- * (precision, basis, weight, D, and the node-tile and point counts to the
- * nearest power of two below) is run once per candidate slab width on its
- * slot and timed; the fastest width serves the class from then on.
- * Requests that set opts.lp_slab themselves are not tuned.  cache_path
- * (may be NULL): a text file of "class = width" lines, read now and
- * rewritten whenever a class is added.  Tuning never changes a result bit.
+ * recurring shapes).  The node tile is fixed at 16 x 16 by the matrix
+ * instruction; the tuned tile dimension is the feature axis: the attributes
+ * per slab, which set the feature tiles of 16 columns a workgroup computes.
+ * enable = 1: the first request of each shape class (precision, basis,
+ * weight kind, D rounded up to a power of two, node count rounded up to a
+ * power of four) is queued to a tuner thread, which times the candidate
+ * widths on its own stream, context and output buffer while the scheduler
+ * serves the class with the library's plan; later requests of the class
+ * take the fastest width.  The tuner's memory (2 x slot_scratch_bytes) is
+ * reserved from the budget when tuning is first enabled
+ * (MLS_ERR_OVER_BUDGET if it does not fit) and kept until the server is
+ * destroyed; a request whose output does not fit it leaves its class on
+ * the library's plan.  Requests that set opts.lp_slab themselves are not
+ * tuned.  cache_path (may be NULL): a text file of "class = width" lines,
+ * read now and rewritten whenever a class is added.  Tuning never changes a
+ * result bit.
  */
 mls_status mls_server_tuning(mls_server* srv, int32_t enable, const char* cache_path);
 
 /* Number of shape classes the tuner holds. */
 int64_t mls_server_tuned_classes(mls_server* srv);
+/* Number of shape classes queued to or being timed by the tuner thread. */
+int64_t mls_server_tuning_pending(mls_server* srv);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,8 @@ EXPORTS = ("mls_status_string", "mls_last_error", "mls_context_create",
            "mls_server_poll", "mls_server_wait", "mls_server_last_error",
            "mls_server_tuning", "mls_server_tuned_classes", "mls_fit_grad", "mls_layout",
            "mls_contour_static", "mls_context_trace", "mls_context_trace_last",
-           "mls_map_bands", "mls_map_adaptive")
+           "mls_map_bands", "mls_map_adaptive", "mls_server_cancel",
+           "mls_server_tuning_pending")
 
 
 class MlsGrid(ctypes.Structure):
@@ -56,7 +57,7 @@ class MlsRequest(ctypes.Structure):
     _fields_ = [("pointset", ctypes.c_uint64), ("basis", ctypes.c_int32),
                 ("weight", MlsWeight), ("grid", MlsGrid), ("precision", ctypes.c_int32),
                 ("opts", MlsSolveOpts), ("d_fields", ctypes.c_void_p),
-                ("d_degree", ctypes.c_void_p)]
+                ("d_degree", ctypes.c_void_p), ("timeout_s", ctypes.c_double)]
 
 
 class MlsResult(ctypes.Structure):
@@ -150,5 +151,9 @@ def load():
     lib.mls_server_tuning.restype = ctypes.c_int
     lib.mls_server_tuned_classes.argtypes = [P]
     lib.mls_server_tuned_classes.restype = ctypes.c_int64
+    lib.mls_server_tuning_pending.argtypes = [P]
+    lib.mls_server_tuning_pending.restype = ctypes.c_int64
+    lib.mls_server_cancel.argtypes = [P, ctypes.c_uint64]
+    lib.mls_server_cancel.restype = ctypes.c_int
     _lib = lib
     return lib

@@ -408,9 +408,10 @@ class ServerError(RuntimeError):
 
 
 class Server:
-    """The served form (mls_server_*): resident point sets, requests admitted
-    onto concurrent slots as they arrive.  Output tensors of submitted
-    requests must stay alive until their result is collected."""
+    """The served form (mls_server_*): resident point sets; requests admitted
+    as they arrive onto slots, 16-bit Gaussian requests of one kernel class
+    batched into persistent kernels.  Output tensors of submitted requests
+    must stay alive until their result is collected."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 2 << 30, slots: int = 4,
                  slot_scratch: int = 64 << 20, tune: bool = False,
@@ -434,6 +435,14 @@ class Server:
 
     def tuned_classes(self) -> int:
         return int(_lib.load().mls_server_tuned_classes(self._ptr))
+
+    def tuning_pending(self) -> int:
+        return int(_lib.load().mls_server_tuning_pending(self._ptr))
+
+    def cancel(self, ticket: int):
+        st = _lib.load().mls_server_cancel(self._ptr, int(ticket))
+        if st != STATUS_OK:
+            raise ServerError(st, "mls_server_cancel")
 
     def close(self):
         if self._ptr:
@@ -472,7 +481,8 @@ class Server:
     def submit(self, pointset: int, grid: dict, out, degree_out=None, basis: str = "linear",
                weight: str = "gaussian", h: float = 0.05, alpha: float = 1.0,
                precision: str = "f64", pivot_tol: float = 1e-8, weight_floor: float = 1e-6,
-               lp_terms: int = 0, lp_slab: int = 0, lp_form: int = 0) -> int:
+               lp_terms: int = 0, lp_slab: int = 0, lp_form: int = 0,
+               timeout_s: float = 0.0) -> int:
         import torch
         # point sets of this server: the outputs must fit them (an unknown
         # id is left to the library, which refuses it without a launch)
@@ -491,7 +501,8 @@ class Server:
                               _lib.MlsSolveOpts(float(pivot_tol), float(weight_floor),
                                                 int(lp_terms), int(lp_slab), int(lp_form)),
                               out.data_ptr(),
-                              None if degree_out is None else degree_out.data_ptr())
+                              None if degree_out is None else degree_out.data_ptr(),
+                              float(timeout_s))
         t = ctypes.c_uint64()
         st = _lib.load().mls_server_submit(self._ptr, ctypes.byref(req), ctypes.byref(t))
         if st != STATUS_OK:

@@ -358,6 +358,7 @@ const char* mls_status_string(mls_status s) {
     case MLS_ERR_CAPACITY: return "MLS_ERR_CAPACITY";
     case MLS_ERR_DEVICE: return "MLS_ERR_DEVICE";
     case MLS_ERR_OVER_BUDGET: return "MLS_ERR_OVER_BUDGET";
+    case MLS_ERR_CANCELLED: return "MLS_ERR_CANCELLED";
     case MLS_ERR_UNSUPPORTED: return "MLS_ERR_UNSUPPORTED";
     case MLS_PENDING: return "MLS_PENDING";
   }
@@ -415,12 +416,16 @@ void mls_context_destroy(mls_context* ctx) {
   delete ctx;
 }
 
-// mls_fit and mls_fit_grad: d_grad (slopes of the local fits) may be NULL.
-static mls_status fit_impl(mls_context* ctx, const float* d_points, const float* d_values,
-                           int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
-                           const mls_grid* grid, int32_t precision,
-                           const mls_solve_opts* opts, float* d_fields, float* d_grad,
-                           uint8_t* d_degree, void* stream) {
+}  // extern "C"
+
+namespace mls {
+
+// Every check of mls_fit / mls_fit_grad (arguments, then the device
+// pointers), and the fit's arguments, without enqueueing anything.
+mls_status fit_prepare(mls_context* ctx, const float* d_points, const float* d_values, int64_t n,
+                       int32_t d, int32_t basis, const mls_weight* weight, const mls_grid* grid,
+                       int32_t precision, const mls_solve_opts* opts, float* d_fields,
+                       float* d_grad, uint8_t* d_degree, FitArgs* out, int* terms_out) {
   // ---- arguments, checked without touching the device ----
   if (basis < MLS_BASIS_CONSTANT || basis > MLS_BASIS_RIGID)
     return fail(MLS_ERR_INVALID_ARG, "basis %d is not an mls_basis", basis);
@@ -490,6 +495,37 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
     return fail(MLS_ERR_UNSUPPORTED, "the inverse-distance weight needs nonzero grid spacing "
                 "(nodes on one position would share their exact hits)");
 
+  if (precision != MLS_PREC_F64) {
+    // The 16-bit contraction accumulates moments in a frame shared by a
+    // 16 x 16 node tile; moving them to a node far from the frame's origin
+    // cancels digits the float32 accumulator cannot spare (the constant basis
+    // has no frame-dependent moments).  Grids that coarse against h are small:
+    // the float64 path serves them.
+    const double extent = mls::lp_tile_extent(grid->dx, grid->dy, weight->h);
+    const double span_max = basis == MLS_BASIS_QUADRATIC ? MLS_LP_MAX_TILE_SPAN_QUADRATIC
+                            : basis == MLS_BASIS_LINEAR  ? MLS_LP_MAX_TILE_SPAN_LINEAR
+                                                         : HUGE_VAL;
+    if (extent > span_max * (1.0 + 1e-12))
+      return fail(MLS_ERR_UNSUPPORTED, "a 16 x 16 node tile spans %.2f h (> %.1f h for this "
+                  "basis); use MLS_PREC_F64 for grids this coarse against h", extent, span_max);
+    if (precision == MLS_PREC_FP16) {
+      // tile-frame features reach |u| <= 8 + half the tile diagonal (in h);
+      // the largest, u^4 times an attribute in [-1, 1], must stay finite
+      const double sx = grid->dx / weight->h, sy = grid->dy / weight->h;
+      const double reach = 8.0 + 0.5 * std::sqrt(256.0 * (sx * sx + sy * sy));
+      const double big = basis == MLS_BASIS_QUADRATIC ? reach * reach * reach * reach
+                         : (basis == MLS_BASIS_LINEAR ? reach * reach : 1.0);
+      if (big > 6.0e4)
+        return fail(MLS_ERR_UNSUPPORTED, "grid spacing %g x %g is too coarse against h = %g for "
+                    "float16 features", grid->dx, grid->dy, weight->h);
+    }
+    if (weight->kind == MLS_W_WENDLAND_C2 &&
+        mls::make_fit_plan(n, d, precision, weight->kind, weight->h, grid->x0, grid->y0, grid->dx,
+                           grid->dy, grid->width, grid->height).list_cap > (int64_t)0xFFFFFFFFu)
+      return fail(MLS_ERR_UNSUPPORTED, "the per-tile point lists of %lld points with h = %g on "
+                  "this grid could exceed 2^32 entries", (long long)n, weight->h);
+  }
+
   // ---- device ----
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return device_fail(e, "hipSetDevice");
@@ -519,10 +555,48 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   a.tau = tau;
   a.floor_w = floor_w;
   a.lp_slab = slab;
-  a.lp_form = form;
   a.fields = d_fields;
   a.deg_out = d_degree;
   a.grads = d_grad;
+  a.lp_form = form;
+  *out = a;
+  *terms_out = terms;
+  return MLS_OK;
+}
+
+void* context_scratch(void* ctx, size_t* bytes) {
+  mls_context* c = (mls_context*)ctx;
+  *bytes = c->fit_scratch.bytes;
+  return c->fit_scratch.ptr;
+}
+
+mls_status_t fit_prepare_c(void* ctx, const float* d_points, const float* d_values, int64_t n,
+                           int32_t d, int32_t basis, const void* weight, const void* grid,
+                           int32_t precision, const void* opts, float* d_fields, float* d_grad,
+                           uint8_t* d_degree, FitArgs* out, int* terms) {
+  g_last_error[0] = '\0';
+  return fit_prepare((mls_context*)ctx, d_points, d_values, n, d, basis,
+                     (const mls_weight*)weight, (const mls_grid*)grid, precision,
+                     (const mls_solve_opts*)opts, d_fields, d_grad, d_degree, out, terms);
+}
+
+}  // namespace mls
+
+extern "C" {
+
+// mls_fit and mls_fit_grad: d_grad (slopes of the local fits) may be NULL.
+static mls_status fit_impl(mls_context* ctx, const float* d_points, const float* d_values,
+                           int64_t n, int32_t d, int32_t basis, const mls_weight* weight,
+                           const mls_grid* grid, int32_t precision,
+                           const mls_solve_opts* opts, float* d_fields, float* d_grad,
+                           uint8_t* d_degree, void* stream) {
+  mls::FitArgs a;
+  int terms = 0;
+  mls_status st = mls::fit_prepare(ctx, d_points, d_values, n, d, basis, weight, grid, precision,
+                                   opts, d_fields, d_grad, d_degree, &a, &terms);
+  if (st != MLS_OK) return st;
+  const int form = a.lp_form;
+  hipError_t e;
   hipStream_t s = (hipStream_t)stream;
   Tracer tr(ctx, s, d_grad ? "fit_grad" : "fit",
             fit_meta(n, d, basis, weight->kind, grid, precision));
@@ -570,35 +644,9 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
     return MLS_OK;
   }
   const bool fp16 = precision == MLS_PREC_FP16;
-  // The 16-bit contraction accumulates moments in a frame shared by a
-  // 16 x 16 node tile; moving them to a node far from the frame's origin
-  // cancels digits the float32 accumulator cannot spare (the constant basis
-  // has no frame-dependent moments).  Grids that coarse against h are small:
-  // the float64 path serves them.
-  const double extent = mls::lp_tile_extent(grid->dx, grid->dy, weight->h);
-  const double span_max = basis == MLS_BASIS_QUADRATIC ? MLS_LP_MAX_TILE_SPAN_QUADRATIC
-                          : basis == MLS_BASIS_LINEAR  ? MLS_LP_MAX_TILE_SPAN_LINEAR
-                                                       : HUGE_VAL;
-  if (extent > span_max * (1.0 + 1e-12))
-    return fail(MLS_ERR_UNSUPPORTED, "a 16 x 16 node tile spans %.2f h (> %.1f h for this "
-                "basis); use MLS_PREC_F64 for grids this coarse against h", extent, span_max);
-  if (fp16) {
-    // tile-frame features reach |u| <= 8 + half the tile diagonal (in h);
-    // the largest, u^4 times an attribute in [-1, 1], must stay finite
-    const double sx = grid->dx / weight->h, sy = grid->dy / weight->h;
-    const double reach = 8.0 + 0.5 * std::sqrt(256.0 * (sx * sx + sy * sy));
-    const double big = basis == MLS_BASIS_QUADRATIC ? reach * reach * reach * reach
-                       : (basis == MLS_BASIS_LINEAR ? reach * reach : 1.0);
-    if (big > 6.0e4)
-      return fail(MLS_ERR_UNSUPPORTED, "grid spacing %g x %g is too coarse against h = %g for "
-                  "float16 features", grid->dx, grid->dy, weight->h);
-  }
   const mls::FitPlan plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h,
                                                grid->x0, grid->y0, grid->dx, grid->dy,
                                                grid->width, grid->height);
-  if (weight->kind == MLS_W_WENDLAND_C2 && plan.list_cap > (int64_t)0xFFFFFFFFu)
-    return fail(MLS_ERR_UNSUPPORTED, "the per-tile point lists of %lld points with h = %g on "
-                "this grid could exceed 2^32 entries", (long long)n, weight->h);
   if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
   if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
   char* base = (char*)ctx->fit_scratch.ptr;

@@ -48,6 +48,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "../../include/mls.h"
 #include "mls_internal.h"
@@ -319,21 +320,22 @@ __device__ __forceinline__ void make_chunk(const LPParams& p, const float* raw, 
   }
 }
 
+// One node tile and attribute slab of a fit: `block` indexes (slab, tile
+// slot) as a launch's workgroup index does.  Every thread of the workgroup
+// calls it with the same arguments.
 template <int DEG, int NTS, int S, typename T, bool WEND, bool CELLS>
-__global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
+__device__ __forceinline__ void lp_tile(const LPParams& p, int block, char* lds_lp) {
   using L = LPLayout<DEG, NTS, S, T>;
   typedef typename Vec8<T>::type vec8;
-  extern __shared__ __attribute__((aligned(16))) char lds_lp[];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool mma = wave < kMmaWaves;
   const int pt = tid - kMmaWaves * 64;   // producer thread index
   // with the cell list, p.slots workgroup slots per slab map to tiles
-  // through the supertile order; empty slots exit before any barrier
+  // through the supertile order; empty slots return before any barrier
   const int per_slab = CELLS ? p.slots : p.tiles;
-  const int slab = blockIdx.x / per_slab;
-  const uint32_t tile_u =
-      CELLS ? p.torder[blockIdx.x % per_slab] : (uint32_t)(blockIdx.x % per_slab);
+  const int slab = block / per_slab;
+  const uint32_t tile_u = CELLS ? p.torder[block % per_slab] : (uint32_t)(block % per_slab);
   if (tile_u == 0xFFFFFFFFu) return;
   const int tile = (int)tile_u;
   const int c0 = (tile % p.tiles_x) * kCols;
@@ -485,6 +487,99 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
                                             p.inv_hd);
       if (p.deg_out && slab == 0) p.deg_out[off] = code;
     }
+  }
+}
+
+template <int DEG, int NTS, int S, typename T, bool WEND, bool CELLS>
+__global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
+  extern __shared__ __attribute__((aligned(16))) char lds_lp[];
+  lp_tile<DEG, NTS, S, T, WEND, CELLS>(p, blockIdx.x, lds_lp);
+}
+
+// Persistent batch of served fits sharing one kernel shape: every
+// workgroup takes (request, block) work items from a device counter until
+// the list is exhausted (every workgroup reaches the end of the list, so the
+// grid drains).  Before an item the request's cancel flag (host memory) is
+// read; a cancelled request's items are counted but not computed, and the
+// request is marked as skipped.  The workgroup that finishes a request's
+// last item sets the request's completion flag in host memory (1: every
+// item computed, 2: items skipped), after a system-scope fence behind all
+// of the request's output writes, so the host sees each request finish
+// while the batch runs on.
+struct LPBatch {
+  const LPParams* __restrict__ reqs;   // [n_req]
+  const uint2* items;          // [n_items] (request, block)
+  const uint32_t* total;       // [n_req] items of each request
+  uint32_t* head;              // next item (zero at launch)
+  uint32_t* done;              // [n_req] finished items (zero at launch)
+  uint32_t* skipped;           // [n_req] nonzero once an item was skipped (zero at launch)
+  uint32_t* complete;          // [n_req] host: 1 or 2 when a request is done
+  const uint32_t* cancel;      // [n_req] host: nonzero = skip the request
+  int n_items;
+};
+
+// The tile body as a call of its own in the batch kernel, so that its
+// registers are allocated apart from the item loop's.
+template <int DEG, int NTS, int S, typename T>
+__device__ __noinline__ void lp_tile_item(const LPParams* __restrict__ pp, int block,
+                                          char* lds_lp) {
+  lp_tile<DEG, NTS, S, T, false, false>(*pp, block, lds_lp);
+}
+
+// Thread 0 finishes the workgroup's previous item and takes the next one
+// in a single branch at the top of the loop; every other branch in the loop
+// is on values held in scalar registers.  (With a second thread-0 branch at
+// the bottom of the loop the compiler threads the path of the other
+// threads from the last barrier straight to the first, and the loop it
+// builds from that runs their path until they leave it, which they never
+// do: no item is taken without thread 0.)
+template <int DEG, int NTS, int S, typename T>
+__global__ __launch_bounds__(kThreads) void fit_lp_batch_kernel(LPBatch b) {
+  extern __shared__ __attribute__((aligned(16))) char lds_lp[];
+  __shared__ int sh_item, sh_skip;
+  int prev_req = -1;   // the request of the item this workgroup finished last
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (prev_req >= 0) {
+        // every thread's output writes are fenced before the barrier that
+        // ended the item
+        const uint32_t prev = atomicAdd(b.done + prev_req, 1u);
+        if (prev + 1 == b.total[prev_req]) {
+          __threadfence();   // every item of the request is counted: see their marks
+          const uint32_t sk = __hip_atomic_load(b.skipped + prev_req, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+          __threadfence_system();
+          __hip_atomic_store(b.complete + prev_req, sk ? 2u : 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      const int it = (int)atomicAdd(b.head, 1u);
+      int skip = 0;
+      if (it < b.n_items) {
+        const uint32_t r = b.items[it].x;
+        skip = __hip_atomic_load(b.cancel + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+        // ordered before this item's count by the fence at the item's end
+        if (skip) __hip_atomic_store(b.skipped + r, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      sh_item = it;
+      sh_skip = skip;
+    }
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(sh_item);
+    const int skip = __builtin_amdgcn_readfirstlane(sh_skip);
+    __syncthreads();
+    if (item >= b.n_items) break;
+    const uint2 w = b.items[item];
+    const int req = __builtin_amdgcn_readfirstlane((int)w.x);
+    const int block = __builtin_amdgcn_readfirstlane((int)w.y);
+    if (!skip) {
+      // read in place (uniform, read-only): fields are loaded where used,
+      // as kernel arguments are, instead of held in registers
+      lp_tile_item<DEG, NTS, S, T>(b.reqs + req, block, lds_lp);
+    }
+    __threadfence();
+    __syncthreads();
+    prev_req = req;
   }
 }
 
@@ -1053,6 +1148,143 @@ void lp_slab_plan(int degree, int D, int forced_ds, int* nts_out, int* ds_out, i
   *nslab_out = best_ns;
 }
 
+// ---- served batches ----
+
+bool lp_batch_class(const FitArgs& a, bool fp16, int terms, LPBatchClass* cls) {
+  if (a.wkind != 0 || a.grads || a.rigid) return false;
+  if (lp_use_shape_form(a.degree, a.D, fp16, a.wkind, false, terms, 0, a.lp_form)) return false;
+  int nts, ds, nslab;
+  lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
+  cls->deg = a.degree;
+  cls->nts = nts;
+  cls->terms = terms;
+  cls->fp16 = fp16;
+  const int64_t tiles = (int64_t)((a.W + kCols - 1) / kCols) * ((a.H + kRows - 1) / kRows);
+  cls->blocks = tiles * nslab;
+  return true;
+}
+
+size_t lp_params_bytes() { return sizeof(LPParams); }
+
+// Parameters of a one-pass fit (launch_fit_lp and the served batches).
+static LPParams dense_lp_params(const FitArgs& a, const float* vals_t, const float* shift,
+                                const float* scale) {
+  int nts, ds, nslab;
+  lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
+  LPParams p{};
+  p.pts = a.pts;
+  p.vals_t = vals_t;
+  p.shift = shift;
+  p.scale = scale;
+  p.n = a.n;
+  p.D = a.D;
+  p.Ds = ds;
+  p.nslab = nslab;
+  p.inv_hd = 1.0 / a.h;
+  p.inv_h = (float)p.inv_hd;
+  p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;
+  p.W = a.W; p.H = a.H;
+  p.tiles_x = (a.W + kCols - 1) / kCols;
+  p.tiles = p.tiles_x * ((a.H + kRows - 1) / kRows);
+  p.tau = a.tau;
+  p.floor_w = a.floor_w;
+  // weight below exp(-64) ~ 1.6e-28 at every node of the tile: the tile
+  // spans at most half its diagonal from the anchor
+  const double sxd = a.dx / a.h, syd = a.dy / a.h;
+  const double half = 0.5 * sqrt((double)(kCols * kCols) * sxd * sxd +
+                                 (double)(kRows * kRows) * syd * syd);
+  const double reach = 8.0 + half;
+  p.cutoff2 = (float)(reach * reach);
+  p.fields = a.fields;
+  p.deg_out = a.deg_out;
+  p.grads = nullptr;
+  p.torder = nullptr;
+  p.tile_start = nullptr;
+  p.tile_list = nullptr;
+  return p;
+}
+
+void lp_params_write(const FitArgs& a, const float* vals_t, const float* shift,
+                     const float* scale, void* out) {
+  const LPParams p = dense_lp_params(a, vals_t, shift, scale);
+  memcpy(out, &p, sizeof(p));
+}
+
+// One workgroup per resident slot of the device (compute units x the
+// kernel's occupancy), at most one per item, at most max_grid if nonzero.
+template <int DEG, int NTS, int S, typename T>
+hipError_t launch_batch_impl(const LPBatch& b, int max_grid, hipStream_t s) {
+  using L = LPLayout<DEG, NTS, S, T>;
+  const size_t lds = (size_t)L::kBytes;
+  const void* fn = (const void*)fit_lp_batch_kernel<DEG, NTS, S, T>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds)) !=
+      hipSuccess)
+    return e;
+  int64_t grid = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  if (grid > b.n_items) grid = b.n_items;
+  if (max_grid > 0 && grid > max_grid) grid = max_grid;
+  if (grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fit_lp_batch_kernel<DEG, NTS, S, T>), dim3((unsigned)grid), dim3(kThreads),
+                     lds, s, b);
+  return hipGetLastError();
+}
+
+template <int DEG, int S, typename T>
+hipError_t launch_batch_nts(const LPBatch& b, int nts, int grid, hipStream_t s) {
+  switch (nts) {
+    case 1: return launch_batch_impl<DEG, 1, S, T>(b, grid, s);
+    case 2: return launch_batch_impl<DEG, 2, S, T>(b, grid, s);
+    case 3: return launch_batch_impl<DEG, 3, S, T>(b, grid, s);
+    case 4: return launch_batch_impl<DEG, 4, S, T>(b, grid, s);
+    case 5: return launch_batch_impl<DEG, 5, S, T>(b, grid, s);
+    case 6: return launch_batch_impl<DEG, 6, S, T>(b, grid, s);
+    case 7: return launch_batch_impl<DEG, 7, S, T>(b, grid, s);
+    default: return launch_batch_impl<DEG, 8, S, T>(b, grid, s);
+  }
+}
+
+template <int S, typename T>
+hipError_t launch_batch_deg(const LPBatch& b, int deg, int nts, int grid, hipStream_t s) {
+  switch (deg) {
+    case 0: return launch_batch_nts<0, S, T>(b, nts, grid, s);
+    case 1: return launch_batch_nts<1, S, T>(b, nts, grid, s);
+    default: return launch_batch_nts<2, S, T>(b, nts, grid, s);
+  }
+}
+
+template <typename T>
+hipError_t launch_batch_terms(const LPBatch& b, const LPBatchClass& c, int grid, hipStream_t s) {
+  switch (c.terms) {
+    case 1: return launch_batch_deg<1, T>(b, c.deg, c.nts, grid, s);
+    case 2: return launch_batch_deg<2, T>(b, c.deg, c.nts, grid, s);
+    default: return launch_batch_deg<3, T>(b, c.deg, c.nts, grid, s);
+  }
+}
+
+hipError_t launch_fit_lp_batch(const LPBatchClass& c, const void* d_params, const uint32_t* d_items,
+                               int n_items, const uint32_t* d_total, uint32_t* d_head,
+                               uint32_t* d_done, uint32_t* d_skipped, uint32_t* h_complete,
+                               const uint32_t* h_cancel, int grid, hipStream_t s) {
+  LPBatch b;
+  b.reqs = (const LPParams*)d_params;
+  b.items = (const uint2*)d_items;
+  b.total = d_total;
+  b.head = d_head;
+  b.done = d_done;
+  b.skipped = d_skipped;
+  b.complete = h_complete;
+  b.cancel = h_cancel;
+  b.n_items = n_items;
+  return c.fp16 ? launch_batch_terms<_Float16>(b, c, grid, s)
+                : launch_batch_terms<__bf16>(b, c, grid, s);
+}
+
 // Largest node offset across a tile, in units of h.
 double lp_tile_extent(double dx, double dy, double h) {
   const double ex = (double)(kCols - 1) * fabs(dx / h), ey = (double)(kRows - 1) * fabs(dy / h);
@@ -1082,34 +1314,9 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
   // that must not change a result bit)
   if (lp_use_shape_form(a.degree, a.D, fp16, a.wkind, a.grads != nullptr, terms, 0,
                         a.lp_form)) {
-    LPParams p{};
-    p.pts = a.pts;
-    p.vals_t = vals_t;
-    p.shift = shift;
-    p.scale = scale;
-    p.n = a.n;
-    p.D = a.D;
+    LPParams p = dense_lp_params(a, vals_t, shift, scale);
     p.nslab = (a.D + kShapeDsCap - 1) / kShapeDsCap;
     p.Ds = (a.D + p.nslab - 1) / p.nslab;
-    p.inv_hd = 1.0 / a.h;
-    p.inv_h = (float)p.inv_hd;
-    p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;
-    p.W = a.W; p.H = a.H;
-    p.tiles_x = (a.W + kCols - 1) / kCols;
-    p.tiles = p.tiles_x * ((a.H + kRows - 1) / kRows);
-    p.tau = a.tau;
-    p.floor_w = a.floor_w;
-    const double sxd = a.dx / a.h, syd = a.dy / a.h;
-    const double half = 0.5 * sqrt((double)(kCols * kCols) * sxd * sxd +
-                                   (double)(kRows * kRows) * syd * syd);
-    const double reach = 8.0 + half;
-    p.cutoff2 = (float)(reach * reach);
-    p.fields = a.fields;
-    p.deg_out = a.deg_out;
-    p.grads = nullptr;
-    p.torder = nullptr;
-    p.tile_start = nullptr;
-    p.tile_list = nullptr;
     const int ntv = (p.Ds + 15) / 16;
     switch (terms) {
       case 1: return launch_shape_deg<1>(p, a.degree, ntv, stream);
@@ -1117,38 +1324,12 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
       default: return launch_shape_deg<3>(p, a.degree, ntv, stream);
     }
   }
+  // the same parameters a served batch passes for the request, so that a
+  // request computes the same bits alone and in a batch
   int nts, ds, nslab;
   lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
-  LPParams p{};
-  p.pts = a.pts;
-  p.vals_t = vals_t;
-  p.shift = shift;
-  p.scale = scale;
-  p.n = a.n;
-  p.D = a.D;
-  p.Ds = ds;
-  p.nslab = nslab;
-  p.inv_hd = 1.0 / a.h;
-  p.inv_h = (float)p.inv_hd;
-  p.x0 = a.x0; p.y0 = a.y0; p.dx = a.dx; p.dy = a.dy;
-  p.W = a.W; p.H = a.H;
-  p.tiles_x = (a.W + kCols - 1) / kCols;
-  p.tiles = p.tiles_x * ((a.H + kRows - 1) / kRows);
-  p.tau = a.tau;
-  p.floor_w = a.floor_w;
-  // weight below exp(-64) ~ 1.6e-28 at every node of the tile: the tile
-  // spans at most half its diagonal from the anchor
-  const double sxd = a.dx / a.h, syd = a.dy / a.h;
-  const double half = 0.5 * sqrt((double)(kCols * kCols) * sxd * sxd +
-                                 (double)(kRows * kRows) * syd * syd);
-  const double reach = 8.0 + half;
-  p.cutoff2 = (float)(reach * reach);
-  p.fields = a.fields;
-  p.deg_out = a.deg_out;
+  LPParams p = dense_lp_params(a, vals_t, shift, scale);
   p.grads = a.grads;
-  p.torder = nullptr;
-  p.tile_start = nullptr;
-  p.tile_list = nullptr;
   const bool wend = a.wkind == 1;
   if (wend) {
     if (!cells) return hipErrorInvalidValue;

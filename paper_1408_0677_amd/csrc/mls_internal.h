@@ -7,6 +7,8 @@
 
 namespace mls {
 
+typedef int mls_status_t;   // an mls_status value
+
 // Everything a fit kernel needs, resolved and validated on the host.
 struct FitArgs {
   const float* pts;     // [n][2]
@@ -48,6 +50,44 @@ hipError_t launch_fit_lp(const FitArgs& a, const float* vals_t, const float* shi
 // Attribute slabs of the 16-bit kernel: `forced_ds` attributes per slab
 // (0 = the cost model's choice); NTS feature tiles of 16 per slab.
 void lp_slab_plan(int degree, int D, int forced_ds, int* nts, int* ds, int* nslab);
+// The checks of mls_fit / mls_fit_grad and the fit's arguments (no device
+// work enqueued); `terms` receives the 16-bit terms per feature.  The
+// caller passes the library's public types through void pointers to keep
+// this header free of them.
+mls_status_t fit_prepare_c(void* ctx, const float* d_points, const float* d_values, int64_t n,
+                           int32_t d, int32_t basis, const void* weight, const void* grid,
+                           int32_t precision, const void* opts, float* d_fields, float* d_grad,
+                           uint8_t* d_degree, FitArgs* out, int* terms);
+
+// A context's fit scratch (reserved with mls_context_reserve): pointer and
+// size.  The served batches stage their requests there.
+void* context_scratch(void* ctx, size_t* bytes);
+
+// Served batches of one-pass 16-bit fits with the Gaussian weight: requests
+// of one class (degree, feature tiles per slab, terms, float16 or bfloat16)
+// share a persistent kernel that takes (request, block) items from a device
+// counter (mls_server.cpp).
+struct LPBatchClass {
+  int deg, nts, terms;
+  bool fp16;
+  int64_t blocks;        // work items of this request (tiles x slabs)
+};
+// False if the request does not run the one-pass Gaussian kernel.
+bool lp_batch_class(const FitArgs& a, bool fp16, int terms, LPBatchClass* cls);
+// The kernel parameters of one request (lp_params_bytes() bytes, opaque).
+size_t lp_params_bytes();
+void lp_params_write(const FitArgs& a, const float* vals_t, const float* shift,
+                     const float* scale, void* out);
+// d_items: n_items (request, block) pairs of uint32; d_total[n_req] items
+// per request; d_head (one word), d_done[n_req] and d_skipped[n_req] zero
+// at launch; h_complete (set to 1, or 2 if items were skipped) and h_cancel
+// host-visible flags per request.  grid: at most this many workgroups (0:
+// one per resident slot of the device).
+hipError_t launch_fit_lp_batch(const LPBatchClass& c, const void* d_params, const uint32_t* d_items,
+                               int n_items, const uint32_t* d_total, uint32_t* d_head,
+                               uint32_t* d_done, uint32_t* d_skipped, uint32_t* h_complete,
+                               const uint32_t* h_cancel, int grid, hipStream_t s);
+
 // Whether the 16-bit fit runs in the two-pass (shape-function) form.
 bool lp_use_shape_form(int degree, int D, bool fp16, int wkind, bool grads, int terms,
                        int forced_ds, int form);

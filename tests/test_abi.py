@@ -153,7 +153,10 @@ def test_server_arguments_rejected_without_device(lib):
     assert lib.mls_server_poll(None, 1, ctypes.byref(res)) == -1
     assert lib.mls_server_tuning(None, 1, None) == -1
     assert lib.mls_server_tuned_classes(None) == 0
+    assert lib.mls_server_tuning_pending(None) == 0
+    assert lib.mls_server_cancel(None, 1) == -1
     assert lib.mls_status_string(-5) == b"MLS_ERR_OVER_BUDGET"
+    assert lib.mls_status_string(-6) == b"MLS_ERR_CANCELLED"
     assert lib.mls_status_string(1) == b"MLS_PENDING"
 
 
@@ -259,3 +262,41 @@ def test_map_arguments_rejected_before_device(lib):
     assert lib.mls_map_adaptive(None, fake, fake, 1, ctypes.byref(g), fake, ctypes.byref(prm),
                                 fake, None) == -1
     assert b"ctx is NULL" in lib.mls_last_error()
+
+
+# binding field names that differ from the header's (Python keywords)
+RENAMED = {"lam": "lambda"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding declares has the header's size and field
+    offsets (a C program built with gcc from include/mls.h prints them)."""
+    import os
+    import shutil
+    import subprocess
+    from paper_1408_0677_amd import _lib
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not found")
+    pairs = {"mls_grid": _lib.MlsGrid, "mls_weight": _lib.MlsWeight,
+             "mls_solve_opts": _lib.MlsSolveOpts, "mls_layout_params": _lib.MlsLayoutParams,
+             "mls_adaptive_params": _lib.MlsAdaptiveParams, "mls_request": _lib.MlsRequest,
+             "mls_result": _lib.MlsResult, "mls_trace_record": _lib.MlsTraceRecord}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mls.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            field = RENAMED.get(fname, fname)
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    expect = []
+    for cname, cls in pairs.items():
+        expect.append(f"{cname} size {ctypes.sizeof(cls)}")
+        for fname, _ in cls._fields_:
+            expect.append(f"{cname} {fname} {getattr(cls, fname).offset}")
+    assert [g for g in got if g] == expect
