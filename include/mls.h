@@ -427,8 +427,9 @@ mls_status mls_map_adaptive(mls_context* ctx, const float* d_fields, const float
  * context with reserved scratch each).  Whenever a slot is free, a
  * scheduler thread gives it the request at the head of the queue together
  * with the later queued requests of the same kernel class (16-bit one-pass
- * fits with the Gaussian weight and no gradients, of one degree, feature
- * tiles per workgroup, terms and format), in arrival order, while their
+ * fits with the Gaussian weight, no gradients and the format's default
+ * lp_terms, of one degree, feature tiles per workgroup and format), in
+ * arrival order, while their
  * staging fits the slot's scratch.  Such a batch runs as one persistent
  * kernel whose workgroups take (request, tile) work items from a device
  * counter; each request's completion flag lives in pinned host memory and
@@ -511,9 +512,10 @@ const char* mls_server_last_error(void);
  * enable = 1: the first request of each shape class (precision, basis,
  * weight kind, D rounded up to a power of two, node count rounded up to a
  * power of four) is queued to a tuner thread, which times the candidate
- * widths on its own stream, context and output buffer while the scheduler
- * serves the class with the library's plan; later requests of the class
- * take the fastest width.  The tuner's memory (2 x slot_scratch_bytes) is
+ * widths (three interleaved rounds, the fastest time of each) on its own
+ * stream, context and output buffer while the scheduler serves the class
+ * with the library's plan; later requests of the class take the fastest
+ * width if it beats the library's plan by at least 5%, else the plan.  The tuner's memory (2 x slot_scratch_bytes) is
  * reserved from the budget when tuning is first enabled
  * (MLS_ERR_OVER_BUDGET if it does not fit) and kept until the server is
  * destroyed; a request whose output does not fit it leaves its class on

@@ -187,6 +187,15 @@ __device__ __forceinline__ float wendland_c2(float s2) {
 }
 
 // Producer: global -> registers for one raw chunk.
+// The input arrays are global memory.  Said explicitly, their loads are
+// global loads also where the compiler cannot see it (parameters read from
+// memory in the served batches) instead of flat loads, which also wait on
+// the LDS counter.
+template <typename V>
+__device__ __forceinline__ const __attribute__((address_space(1))) V* global_ptr(const V* q) {
+  return (const __attribute__((address_space(1))) V*)q;
+}
+
 template <int DEG, int NTS, int S, typename T>
 __device__ __forceinline__ void raw_load(const LPParams& p, const Chunk& ch, int d0, int Ds,
                                          int pt, float (&r)[LPLayout<DEG, NTS, S, T>::kRawIt]) {
@@ -198,10 +207,11 @@ __device__ __forceinline__ void raw_load(const LPParams& p, const Chunk& ch, int
     if (ch.valid && e < (2 + Ds) * KT) {
       const int row = e / KT, k = e - row * KT;
       if (k < ch.kn) {
-        const int64_t gi = p.tile_list ? (int64_t)p.tile_list[ch.k + k] : ch.k + k;
-        if (row == 0) v = p.pts[2 * gi];
-        else if (row == 1) v = p.pts[2 * gi + 1];
-        else v = p.vals_t[(int64_t)(d0 + row - 2) * p.n + gi];
+        const int64_t gi =
+            p.tile_list ? (int64_t)global_ptr(p.tile_list)[ch.k + k] : ch.k + k;
+        if (row == 0) v = global_ptr(p.pts)[2 * gi];
+        else if (row == 1) v = global_ptr(p.pts)[2 * gi + 1];
+        else v = global_ptr(p.vals_t)[(int64_t)(d0 + row - 2) * p.n + gi];
       }
     }
     r[it] = v;
@@ -501,11 +511,16 @@ __global__ __launch_bounds__(kThreads) void fit_lp_kernel(LPParams p) {
 // the list is exhausted (every workgroup reaches the end of the list, so the
 // grid drains).  Before an item the request's cancel flag (host memory) is
 // read; a cancelled request's items are counted but not computed, and the
-// request is marked as skipped.  The workgroup that finishes a request's
-// last item sets the request's completion flag in host memory (1: every
-// item computed, 2: items skipped), after a system-scope fence behind all
-// of the request's output writes, so the host sees each request finish
-// while the batch runs on.
+// request is marked as skipped.  Items are listed request by request, so a
+// workgroup meets each request in one run of items; when it moves on to the
+// next request (or the list ends) it releases its output writes at device
+// scope and adds the run's length to the request's count.  The workgroup
+// whose addition completes a request acquires the other additions and sets
+// the request's completion flag in host memory (1: every item computed, 2:
+// items skipped) with a system-scope release, so the host sees each request
+// finish, its outputs written, while the batch runs on.  (A release per
+// item would write back the L2 after every tile, and costs about a tenth of
+// the batch's time.)
 struct LPBatch {
   const LPParams* __restrict__ reqs;   // [n_req]
   const uint2* items;          // [n_items] (request, block)
@@ -519,46 +534,48 @@ struct LPBatch {
 };
 
 // The tile body as a call of its own in the batch kernel, so that its
-// registers are allocated apart from the item loop's.
+// registers are allocated apart from the item loop's.  Arguments of a call
+// travel in vector registers and read as per-lane values; the parameter
+// address and the block are made scalar again here, so that the parameters
+// are loaded through the scalar cache as kernel arguments are, and the
+// work area is named as the dynamic LDS array itself, so that its accesses
+// are LDS instructions rather than flat ones.
 template <int DEG, int NTS, int S, typename T>
-__device__ __noinline__ void lp_tile_item(const LPParams* __restrict__ pp, int block,
-                                          char* lds_lp) {
-  lp_tile<DEG, NTS, S, T, false, false>(*pp, block, lds_lp);
+__device__ __noinline__ void lp_tile_item(const LPParams* __restrict__ pp, int block) {
+  extern __shared__ __attribute__((aligned(16))) char lds_lp[];
+  // the parameter block is written before the launch and only read by the
+  // kernel: in the constant address space its loads are scalar loads that
+  // the compiler may repeat instead of holding their values in registers
+  const uint64_t a = (uint64_t)(uintptr_t)pp;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  typedef const __attribute__((address_space(4))) LPParams* ConstParams;
+  const ConstParams pc = (ConstParams)(uintptr_t)(((uint64_t)hi << 32) | lo);
+  lp_tile<DEG, NTS, S, T, false, false>(*(const LPParams*)pc,
+                                        __builtin_amdgcn_readfirstlane(block), lds_lp);
 }
 
-// Thread 0 finishes the workgroup's previous item and takes the next one
-// in a single branch at the top of the loop; every other branch in the loop
-// is on values held in scalar registers.  (With a second thread-0 branch at
-// the bottom of the loop the compiler threads the path of the other
-// threads from the last barrier straight to the first, and the loop it
-// builds from that runs their path until they leave it, which they never
-// do: no item is taken without thread 0.)
+// Thread 0 takes the next item in a branch at the top of the loop; it
+// counts a finished run of items in a second branch, under a condition held
+// in scalar registers, and every path from there back to the top of the
+// loop passes a barrier.  (With only the back edge between two thread-0
+// branches the compiler threads the path of the other threads from the
+// last barrier straight to the first, and the loop it builds from that runs
+// their path until they leave it, which they never do: no item is taken
+// without thread 0.)
 template <int DEG, int NTS, int S, typename T>
 __global__ __launch_bounds__(kThreads) void fit_lp_batch_kernel(LPBatch b) {
-  extern __shared__ __attribute__((aligned(16))) char lds_lp[];
   __shared__ int sh_item, sh_skip;
-  int prev_req = -1;   // the request of the item this workgroup finished last
+  int cur_req = -1;       // request of the current run of items
+  uint32_t cur_cnt = 0;   // items of the run finished here, not yet counted
   for (;;) {
     if (threadIdx.x == 0) {
-      if (prev_req >= 0) {
-        // every thread's output writes are fenced before the barrier that
-        // ended the item
-        const uint32_t prev = atomicAdd(b.done + prev_req, 1u);
-        if (prev + 1 == b.total[prev_req]) {
-          __threadfence();   // every item of the request is counted: see their marks
-          const uint32_t sk = __hip_atomic_load(b.skipped + prev_req, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-          __threadfence_system();
-          __hip_atomic_store(b.complete + prev_req, sk ? 2u : 1u, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-      }
       const int it = (int)atomicAdd(b.head, 1u);
       int skip = 0;
       if (it < b.n_items) {
         const uint32_t r = b.items[it].x;
         skip = __hip_atomic_load(b.cancel + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
-        // ordered before this item's count by the fence at the item's end
+        // released with the run's count
         if (skip) __hip_atomic_store(b.skipped + r, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       sh_item = it;
@@ -568,18 +585,37 @@ __global__ __launch_bounds__(kThreads) void fit_lp_batch_kernel(LPBatch b) {
     const int item = __builtin_amdgcn_readfirstlane(sh_item);
     const int skip = __builtin_amdgcn_readfirstlane(sh_skip);
     __syncthreads();
-    if (item >= b.n_items) break;
-    const uint2 w = b.items[item];
-    const int req = __builtin_amdgcn_readfirstlane((int)w.x);
+    const bool more = item < b.n_items;
+    const uint2 w = more ? b.items[item] : make_uint2(0xFFFFFFFFu, 0u);
+    const int req = __builtin_amdgcn_readfirstlane((int)w.x);   // -1 past the end
     const int block = __builtin_amdgcn_readfirstlane((int)w.y);
+    if (cur_cnt > 0 && req != cur_req) {
+      // the run of cur_req ends here: release its output writes, count it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(b.done + cur_req, cur_cnt);
+        if (prev + cur_cnt == b.total[cur_req]) {
+          // every item of the request is counted: acquire the other runs'
+          // releases (and skip marks), then publish to the host
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          const uint32_t sk = __hip_atomic_load(b.skipped + cur_req, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(b.complete + cur_req, sk ? 2u : 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      cur_cnt = 0;
+    }
+    if (!more) break;
+    cur_req = req;
     if (!skip) {
       // read in place (uniform, read-only): fields are loaded where used,
       // as kernel arguments are, instead of held in registers
-      lp_tile_item<DEG, NTS, S, T>(b.reqs + req, block, lds_lp);
+      lp_tile_item<DEG, NTS, S, T>(b.reqs + req, block);
     }
-    __threadfence();
+    ++cur_cnt;
     __syncthreads();
-    prev_req = req;
   }
 }
 
@@ -1152,6 +1188,8 @@ void lp_slab_plan(int degree, int D, int forced_ds, int* nts_out, int* ds_out, i
 
 bool lp_batch_class(const FitArgs& a, bool fp16, int terms, LPBatchClass* cls) {
   if (a.wkind != 0 || a.grads || a.rigid) return false;
+  // batch kernels exist for each format's default term count
+  if (terms != (fp16 ? 2 : 3)) return false;
   if (lp_use_shape_form(a.degree, a.D, fp16, a.wkind, false, terms, 0, a.lp_form)) return false;
   int nts, ds, nslab;
   lp_slab_plan(a.degree, a.D, a.lp_slab, &nts, &ds, &nslab);
@@ -1258,14 +1296,6 @@ hipError_t launch_batch_deg(const LPBatch& b, int deg, int nts, int grid, hipStr
   }
 }
 
-template <typename T>
-hipError_t launch_batch_terms(const LPBatch& b, const LPBatchClass& c, int grid, hipStream_t s) {
-  switch (c.terms) {
-    case 1: return launch_batch_deg<1, T>(b, c.deg, c.nts, grid, s);
-    case 2: return launch_batch_deg<2, T>(b, c.deg, c.nts, grid, s);
-    default: return launch_batch_deg<3, T>(b, c.deg, c.nts, grid, s);
-  }
-}
 
 hipError_t launch_fit_lp_batch(const LPBatchClass& c, const void* d_params, const uint32_t* d_items,
                                int n_items, const uint32_t* d_total, uint32_t* d_head,
@@ -1281,8 +1311,9 @@ hipError_t launch_fit_lp_batch(const LPBatchClass& c, const void* d_params, cons
   b.complete = h_complete;
   b.cancel = h_cancel;
   b.n_items = n_items;
-  return c.fp16 ? launch_batch_terms<_Float16>(b, c, grid, s)
-                : launch_batch_terms<__bf16>(b, c, grid, s);
+  if (c.terms != (c.fp16 ? 2 : 3)) return hipErrorInvalidValue;
+  return c.fp16 ? launch_batch_deg<2, _Float16>(b, c.deg, c.nts, grid, s)
+                : launch_batch_deg<3, __bf16>(b, c.deg, c.nts, grid, s);
 }
 
 // Largest node offset across a tile, in units of h.

@@ -72,7 +72,8 @@ struct LPBatchClass {
   bool fp16;
   int64_t blocks;        // work items of this request (tiles x slabs)
 };
-// False if the request does not run the one-pass Gaussian kernel.
+// False if the request does not run the one-pass Gaussian kernel with its
+// format's default term count (3 bfloat16, 2 float16 terms).
 bool lp_batch_class(const FitArgs& a, bool fp16, int terms, LPBatchClass* cls);
 // The kernel parameters of one request (lp_params_bytes() bytes, opaque).
 size_t lp_params_bytes();

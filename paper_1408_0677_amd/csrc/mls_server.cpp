@@ -261,37 +261,44 @@ void prune_psets(mls_server* s) {
 }
 
 // Time the candidate widths of one class on the tuner's own stream, context
-// and output buffer (lock not held); 0 = keep the library's plan.
+// and output buffer (lock not held); 0 = keep the library's plan.  The
+// device is shared with the slots, so each width is timed in three rounds,
+// interleaved with the others, and keeps its fastest time; a width replaces
+// the library's plan only when it is at least 5% faster.
 int tune_job(mls_server* s, const TuneJob& job) {
   const size_t out_bytes = (size_t)job.ps.d * job.req.grid.width * job.req.grid.height * 4;
   if (out_bytes > s->slot_scratch) return 0;
-  int best = 0;
-  float best_ms = 0.0f;
-  for (int c : slab_candidates(job.req.basis, job.ps.d)) {
-    mls_solve_opts o = job.req.opts;
-    o.lp_slab = c;
-    float ms = 0.0f;
-    bool good = true;
-    for (int rep = 0; rep < 2 && good; ++rep) {   // the first run loads the kernel
-      good = hipEventRecord(s->tune_e0, s->tune_stream) == hipSuccess;
+  int nts0, plan_ds, nslab0;
+  mls::lp_slab_plan(job.req.basis, job.ps.d, 0, &nts0, &plan_ds, &nslab0);
+  std::vector<int> cands = slab_candidates(job.req.basis, job.ps.d);
+  if (std::find(cands.begin(), cands.end(), plan_ds) == cands.end()) cands.push_back(plan_ds);
+  std::vector<float> best(cands.size(), 0.0f);
+  for (int round = 0; round < 4; ++round) {   // round 0 loads the kernels
+    for (size_t k = 0; k < cands.size(); ++k) {
+      mls_solve_opts o = job.req.opts;
+      o.lp_slab = cands[k];
+      float ms = 0.0f;
+      bool good = hipEventRecord(s->tune_e0, s->tune_stream) == hipSuccess;
       good = good && mls_fit(s->tune_ctx, job.ps.pts, job.ps.vals, job.ps.n, job.ps.d,
                              job.req.basis, &job.req.weight, &job.req.grid, job.req.precision,
                              &o, (float*)s->tune_out, nullptr, (void*)s->tune_stream) == MLS_OK;
       good = good && hipEventRecord(s->tune_e1, s->tune_stream) == hipSuccess;
       good = good && hipEventSynchronize(s->tune_e1) == hipSuccess;
       good = good && hipEventElapsedTime(&ms, s->tune_e0, s->tune_e1) == hipSuccess;
-    }
-    if (!good) {
-      (void)hipGetLastError();
-      (void)hipStreamSynchronize(s->tune_stream);
-      continue;
-    }
-    if (best == 0 || ms < best_ms) {
-      best = c;
-      best_ms = ms;
+      if (!good) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s->tune_stream);
+        return 0;
+      }
+      if (round > 0 && (best[k] == 0.0f || ms < best[k])) best[k] = ms;
     }
   }
-  return best;
+  size_t arg = 0, plan = 0;
+  for (size_t k = 0; k < cands.size(); ++k) {
+    if (best[k] < best[arg]) arg = k;
+    if (cands[k] == plan_ds) plan = k;
+  }
+  return best[arg] < 0.95f * best[plan] ? cands[arg] : 0;
 }
 
 void tuner_main(mls_server* s) {
