@@ -147,8 +147,10 @@ def serve_bench(args):
     reqs = wl.c4_requests(count=args.requests)
     dev = torch.device("cuda:0")
     budget = 2 << 30
-    # a slot stages a whole batch: room for about 16 of the largest requests
-    slot_scratch = 16 * max(api.fit_scratch_bytes(r.n, r.d, r.grid, "fp16") for r in reqs) + \
+    # a slot stages a whole batch (room for about 16 of the largest 16-bit
+    # requests) or one float64 request (its Gaussian factor tables)
+    slot_scratch = max(16 * max(api.fit_scratch_bytes(r.n, r.d, r.grid, "fp16") for r in reqs),
+                       max(api.fit_scratch_bytes(r.n, r.d, r.grid, "f64") for r in reqs)) + \
         (1 << 20)
     # points + slots + the tuner's context scratch and output buffer
     srv = api.Server(0, budget + (args.slots + 2) * slot_scratch, args.slots, slot_scratch)

@@ -194,7 +194,9 @@ void mls_context_destroy(mls_context* ctx);
  * device cell list); the inverse-distance weight with MLS_PREC_F64 on grids
  * with nonzero dx and dy (a node that coincides exactly with data points
  * takes the mean of their values, degree code 254; library scratch of about
- * 16 n bytes).  Other combinations return MLS_ERR_UNSUPPORTED.  The 16-bit precisions
+ * 16 n bytes; the Gaussian on MLS_PREC_F64 uses scratch for its factor
+ * tables, see mls_fit_scratch_bytes).  Other combinations return
+ * MLS_ERR_UNSUPPORTED.  The 16-bit precisions
  * also return MLS_ERR_UNSUPPORTED when a node tile spans more than
  * MLS_LP_MAX_TILE_SPAN_<basis> (linear, quadratic), and MLS_PREC_FP16 when
  * tile-frame features would leave the float16 range; MLS_PREC_F64 serves
@@ -293,8 +295,12 @@ mls_status mls_context_trace(mls_context* ctx, int32_t enable, const char* jsonl
 mls_status mls_context_trace_last(mls_context* ctx, mls_trace_record* out);
 
 /*
- * Device scratch bytes mls_fit needs for this request (0 for MLS_PREC_F64);
- * 0 also for invalid arguments.
+ * Device scratch bytes mls_fit needs for this request; 0 also for invalid
+ * arguments.  MLS_PREC_F64 with the Gaussian weight tabulates the weight
+ * factors of every grid column and row once per call, 8 x (n rounded up to
+ * 64) x (width and height each rounded up to 16) bytes, when that is at most
+ * 512 MiB (beyond, the factors are generated per tile and no scratch is
+ * needed); the inverse-distance weight needs about 16 n bytes.
  */
 size_t mls_fit_scratch_bytes(int64_t n, int32_t d, int32_t precision,
                              const mls_weight* weight, const mls_grid* grid);

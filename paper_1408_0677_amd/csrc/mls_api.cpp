@@ -272,6 +272,11 @@ FitPlan make_fit_plan(int64_t n, int32_t d, int32_t precision, int32_t wkind, do
     return o;
   };
   if (precision == MLS_PREC_F64) {
+    // the Gaussian's factor tables, when they fit the cap
+    if (wkind == MLS_W_GAUSSIAN) {
+      p.gtab_bytes = f64_table_bytes(n, W, H);
+      if (p.gtab_bytes) p.o_gtab = carve(p.gtab_bytes);
+    }
     // the inverse-distance weight's exact-hit pass sorts (node, point) keys
     if (wkind == MLS_W_INVPOW) {
       p.o_keys = carve(4 * (size_t)n);
@@ -559,6 +564,7 @@ mls_status fit_prepare(mls_context* ctx, const float* d_points, const float* d_v
   a.deg_out = d_degree;
   a.grads = d_grad;
   a.lp_form = form;
+  a.gtab = nullptr;
   *out = a;
   *terms_out = terms;
   return MLS_OK;
@@ -601,12 +607,13 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
   Tracer tr(ctx, s, d_grad ? "fit_grad" : "fit",
             fit_meta(n, d, basis, weight->kind, grid, precision));
   if (precision == MLS_PREC_F64) {
-    mls::FitPlan plan{};
-    if (weight->kind == MLS_W_INVPOW) {
-      plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h, grid->x0, grid->y0,
-                                grid->dx, grid->dy, grid->width, grid->height);
+    const mls::FitPlan plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h,
+                                                 grid->x0, grid->y0, grid->dx, grid->dy,
+                                                 grid->width, grid->height);
+    if (plan.total > 0) {
       if ((st = ensure_scratch(ctx->fit_scratch, plan.total)) != MLS_OK) return st;
       if ((st = scratch_acquire(ctx, s)) != MLS_OK) return st;
+      if (plan.gtab_bytes) a.gtab = (double*)((char*)ctx->fit_scratch.ptr + plan.o_gtab);
     }
     e = mls::launch_fit_f64(a, s);
     if (e != hipSuccess) return device_fail(e, "fit kernel launch");
@@ -641,7 +648,7 @@ static mls_status fit_impl(mls_context* ctx, const float* d_points, const float*
       return scratch_release(ctx, s);
     }
     tr.finish();
-    return MLS_OK;
+    return plan.total > 0 ? scratch_release(ctx, s) : MLS_OK;
   }
   const bool fp16 = precision == MLS_PREC_FP16;
   const mls::FitPlan plan = mls::make_fit_plan(n, d, precision, weight->kind, weight->h,

@@ -14,8 +14,12 @@
 //   1. point coordinates -> LDS (tile-frame u, float64),
 //   2. Gaussian weight factors gx[col][k] = exp(-((x_k - p_col)/h)^2) and
 //      gy[row][k] (the Gaussian separates on a grid, so a tile needs
-//      16 + 4R exponentials per point instead of 64R), and the feature
-//      block G[j][k] in float64,
+//      16 + 4R factors per point instead of 64R), and the feature block
+//      G[j][k] in float64.  The factors are either copied from tables of
+//      every grid column and row built once per launch (when they fit the
+//      scratch cap) or generated per tile by a stepping recurrence; the
+//      copy costs load and LDS instructions, which overlap the matrix
+//      cores, where the recurrence costs vector instructions, which do not,
 //   3. MFMA sweep: the A operand (node x point weight) is gx * gy, built in
 //      registers; B is read from G.  Within each group of 16 points a lane
 //      supplies points k0 + 4 (lane / 16) + j for MFMA j = 0..3, so it reads
@@ -72,10 +76,15 @@ constexpr int kEpiWaves = MLS_F64_EPI_WAVES;
 struct F64Params {
   const float* pts;
   const float* vals;
+  // Gaussian factor tables (WM_TABLE kernels): rows [0, tab_cols) are the
+  // grid columns, rows tab_cols + r the grid rows; tab_n points per row
+  const double* tab;
+  int64_t tab_n;
+  int tab_cols;
   int64_t n;
   int D, F;
   double h, inv_h;
-  double alpha;        // inverse-distance exponent (INV kernels)
+  double alpha;        // inverse-distance exponent (WM_INV kernels)
   double x0, y0, dx, dy;
   int W, H, tiles_x;
   double tau, floor_w;
@@ -84,6 +93,11 @@ struct F64Params {
   float* grads;        // [D][2][H][W] or null
   bool rigid;          // rigid map (EPI 2 kernels)
 };
+
+// Weight modes of the kernel: the Gaussian with per-tile factors from a
+// stepping recurrence, the inverse-distance weight per pair, the Gaussian
+// with factors copied from per-launch tables.
+constexpr int WM_GAUSS = 0, WM_INV = 1, WM_TABLE = 2;
 
 template <int DEG, int NT, int R>
 struct F64Layout {
@@ -96,6 +110,8 @@ struct F64Layout {
   static constexpr int kDMax = (kFP - nmom) / m;
   static constexpr int kValRegs =
       kDMax > 0 ? (KT * kDMax + kThreads - 1) / kThreads : 1;
+  // per-thread registers holding one chunk of table factors (16 + 4R rows)
+  static constexpr int kTabRegs = ((kCols + kWaves * R) * KT + kThreads - 1) / kThreads;
   // chunk phase
   static constexpr int kUx = 0;                          // [KT] tile-frame u_x
   static constexpr int kUy = kUx + KT;                   // [KT]
@@ -146,8 +162,9 @@ __device__ __forceinline__ void read4(const double* src, double* dst) {
 // extra solves raise the epilogue's register count, so they are separate
 // instantiations and the plain kernels keep two workgroups per CU), 2 the
 // rigid map of 2-vector values from the linear moments.
-template <int DEG, int NT, int R, bool INV, int EPI>
+template <int DEG, int NT, int R, int WM, int EPI>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
+  constexpr bool INV = WM == WM_INV;
   using L = F64Layout<DEG, NT, R>;
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
   constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
@@ -199,6 +216,21 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     }
   };
   prefetch(0);
+  // table factors of a chunk: row e / KT of the tile's 16 + 4R rows, point
+  // e % KT (consecutive threads read consecutive points of a row)
+  double tv[L::kTabRegs];
+  auto tab_load = [&](int64_t k0) {
+#pragma unroll
+    for (int it = 0; it < L::kTabRegs; ++it) {
+      const int e = tid + it * kThreads;
+      const int row = e / KT, k = e % KT;
+      if (row < kCols + L::kRows) {
+        const int64_t trow = row < kCols ? (int64_t)(c0 + row)
+                                         : (int64_t)p.tab_cols + r0 + (row - kCols);
+        tv[it] = p.tab[trow * p.tab_n + k0 + k];
+      }
+    }
+  };
 
   // Gaussian step factors of the tile (exp(-2 s^2) per node step)
   const double sx = p.dx * p.inv_h, sy = p.dy * p.inv_h;
@@ -227,7 +259,11 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
 
   for (int64_t k0 = 0; k0 < p.n; k0 += KT) {
     const int kn = (int)((p.n - k0) < KT ? (p.n - k0) : KT);
-    for (int e = tid; e < 4 * KT; e += kThreads) {
+    // table factors of this chunk: loaded now, stored after the monomials
+    // and features, so that the loads' latency overlaps that work and the
+    // registers are not held during the sweep
+    if (WM == WM_TABLE) tab_load(k0);
+    for (int e = tid; e < (WM == WM_TABLE ? 0 : 4 * KT); e += kThreads) {
       // 2a. separable Gaussian factors g_c = exp(-(u - e_c)^2), e_c = (c - c_mid) s,
       //     for one point, one axis and one direction.  Start at the node
       //     nearest to u (the largest factor) and step outwards:
@@ -316,6 +352,16 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
         }
       }
     }
+    if (WM == WM_TABLE) {
+      // 2a from the tables (zero past n)
+#pragma unroll
+      for (int it = 0; it < L::kTabRegs; ++it) {
+        const int e = tid + it * kThreads;
+        const int row = e / KT, k = e % KT;
+        if (row < kCols) gx[row * KS + k] = tv[it];
+        else if (row < kCols + L::kRows) gy[(row - kCols) * KS + k] = tv[it];
+      }
+    }
     // next chunk's raw data: in flight during the MFMA sweep
     if (k0 + KT < p.n) prefetch(k0 + KT);
     __syncthreads();
@@ -401,7 +447,7 @@ __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stri
   }
 }
 
-template <int DEG, int NT, int R, bool INV, int EPI>
+template <int DEG, int NT, int R, int WM, int EPI>
 hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   using L = F64Layout<DEG, NT, R>;
   F64Params p = prm;
@@ -409,48 +455,69 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   const int tiles_y = (p.H + L::kRows - 1) / L::kRows;
   p.tiles_x = tiles_x;
   const size_t lds_bytes = sizeof(double) * (size_t)L::kDoubles;
-  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, INV, EPI>,
+  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, WM, EPI>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
-  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, INV, EPI>), dim3((unsigned)blocks), dim3(kThreads),
+  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, WM, EPI>), dim3((unsigned)blocks), dim3(kThreads),
                      lds_bytes, s, p);
   return hipGetLastError();
 }
 
 // R (row strips per wave) trades accumulator registers against the number
 // of Gaussian factors per tile.
-template <int DEG, int NT, bool INV>
+template <int DEG, int NT, int WM>
 hipError_t launch_nt(const F64Params& p, hipStream_t s) {
   constexpr int R = NT <= 3 ? 4 : (NT <= 6 ? 2 : 1);
   if (p.rigid) {
-    if constexpr (DEG == 1 && NT == 1) return launch_impl<DEG, NT, R, INV, 2>(p, s);
+    if constexpr (DEG == 1 && NT == 1) return launch_impl<DEG, NT, R, WM, 2>(p, s);
     return hipErrorInvalidValue;
   }
-  return p.grads ? launch_impl<DEG, NT, R, INV, 1>(p, s) : launch_impl<DEG, NT, R, INV, 0>(p, s);
+  return p.grads ? launch_impl<DEG, NT, R, WM, 1>(p, s) : launch_impl<DEG, NT, R, WM, 0>(p, s);
 }
 
-template <int DEG, bool INV>
+template <int DEG, int WM>
 hipError_t launch_deg(const F64Params& p, int nt, hipStream_t s) {
   switch (nt) {
-    case 1: return launch_nt<DEG, 1, INV>(p, s);
-    case 2: return launch_nt<DEG, 2, INV>(p, s);
-    case 3: return launch_nt<DEG, 3, INV>(p, s);
-    case 4: return launch_nt<DEG, 4, INV>(p, s);
-    case 5: case 6: return launch_nt<DEG, 6, INV>(p, s);
-    case 7: case 8: return launch_nt<DEG, 8, INV>(p, s);
-    case 9: case 10: case 11: case 12: return launch_nt<DEG, 12, INV>(p, s);
-    default: return launch_nt<DEG, 16, INV>(p, s);
+    case 1: return launch_nt<DEG, 1, WM>(p, s);
+    case 2: return launch_nt<DEG, 2, WM>(p, s);
+    case 3: return launch_nt<DEG, 3, WM>(p, s);
+    case 4: return launch_nt<DEG, 4, WM>(p, s);
+    case 5: case 6: return launch_nt<DEG, 6, WM>(p, s);
+    case 7: case 8: return launch_nt<DEG, 8, WM>(p, s);
+    case 9: case 10: case 11: case 12: return launch_nt<DEG, 12, WM>(p, s);
+    default: return launch_nt<DEG, 16, WM>(p, s);
   }
 }
 
-template <bool INV>
+template <int WM>
 hipError_t launch_kind(const F64Params& p, int degree, int nt, hipStream_t s) {
   switch (degree) {
-    case 0: return launch_deg<0, INV>(p, nt, s);
-    case 1: return launch_deg<1, INV>(p, nt, s);
-    default: return launch_deg<2, INV>(p, nt, s);
+    case 0: return launch_deg<0, WM>(p, nt, s);
+    case 1: return launch_deg<1, WM>(p, nt, s);
+    default: return launch_deg<2, WM>(p, nt, s);
+  }
+}
+
+// Gaussian factor tables: row r < cols is exp(-((x_k - (x0 + r dx)) / h)^2)
+// over the points k, row cols + r the same with y and y0 + r dy; zero for
+// k >= n.  Rows past the grid serve the padding nodes of edge tiles.
+__global__ __launch_bounds__(256) void gauss_table_kernel(const float* __restrict__ pts, int64_t n,
+                                                          int64_t tab_n, int cols, double x0,
+                                                          double dx, double y0, double dy,
+                                                          double inv_h, double* __restrict__ tab) {
+  const int row = blockIdx.y;
+  const bool xr = row < cols;
+  const double c = xr ? x0 + (double)row * dx : y0 + (double)(row - cols) * dy;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < tab_n;
+       k += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    if (k < n) {
+      const double u = ((double)pts[2 * k + (xr ? 0 : 1)] - c) * inv_h;
+      v = exp(-(u * u));
+    }
+    tab[row * tab_n + k] = v;
   }
 }
 
@@ -463,6 +530,9 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   F64Params p;
   p.pts = a.pts;
   p.vals = a.vals;
+  p.tab = nullptr;
+  p.tab_n = 0;
+  p.tab_cols = 0;
   p.n = a.n;
   p.D = a.D;
   p.F = F;
@@ -478,8 +548,28 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   p.deg_out = a.deg_out;
   p.grads = a.grads;
   p.rigid = a.rigid;
-  if (a.wkind == 2) return launch_kind<true>(p, a.degree, nt, stream);   // inverse distance
-  return launch_kind<false>(p, a.degree, nt, stream);                    // Gaussian
+  if (a.wkind == 2) return launch_kind<WM_INV>(p, a.degree, nt, stream);   // inverse distance
+  if (!a.gtab) return launch_kind<WM_GAUSS>(p, a.degree, nt, stream);
+  p.tab = a.gtab;
+  p.tab_n = f64_table_points(a.n);
+  p.tab_cols = f64_table_rows(a.W);
+  const int rows = p.tab_cols + f64_table_rows(a.H);
+  const int64_t per_row = (p.tab_n + 255) / 256;
+  const unsigned bx = (unsigned)(per_row < 64 ? per_row : 64);
+  hipLaunchKernelGGL(gauss_table_kernel, dim3(bx, (unsigned)rows), dim3(256), 0, stream, a.pts,
+                     a.n, p.tab_n, p.tab_cols, a.x0, a.dx, a.y0, a.dy, p.inv_h, a.gtab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_kind<WM_TABLE>(p, a.degree, nt, stream);
+}
+
+int64_t f64_table_points(int64_t n) { return (n + KT - 1) / KT * KT; }
+int f64_table_rows(int cells) { return (cells + kCols - 1) / kCols * kCols; }
+
+size_t f64_table_bytes(int64_t n, int32_t W, int32_t H) {
+  const double bytes = 8.0 * (double)f64_table_points(n) *
+                       (double)(f64_table_rows(W) + f64_table_rows(H));
+  return bytes <= (double)kF64TableCap ? (size_t)bytes : 0;
 }
 
 }  // namespace mls

@@ -27,6 +27,7 @@ struct FitArgs {
   int32_t lp_form;      // 16-bit paths: 0 the library's choice, 1 one pass, 2 two passes
   float* grads;         // [D][2][H][W] slopes of the local fits, or null
   bool rigid;           // rigid map of 2-vector values (degree 1 moments, D = 2)
+  double* gtab;         // float64 Gaussian: factor tables in scratch, or null
 };
 
 // Number of basis terms m and of distinct moment monomials for a degree.
@@ -35,7 +36,16 @@ __host__ __device__ constexpr int moment_terms(int deg) { return deg == 0 ? 1 : 
 
 // Float64 matrix-core fit (Gaussian or inverse-distance weight).  Returns a
 // hipError_t.  With the inverse-distance weight, launch_hits must follow.
+// With a.gtab (f64_table_bytes of scratch) the Gaussian factors of every
+// grid column and row are tabulated first and copied by the tiles.
 hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream);
+// Float64 Gaussian factor tables: points padded to the chunk, columns and
+// rows padded to the tile; 0 bytes when the tables would pass the cap (the
+// kernel then generates the factors per tile).
+constexpr size_t kF64TableCap = (size_t)512 << 20;
+int64_t f64_table_points(int64_t n);
+int f64_table_rows(int cells);
+size_t f64_table_bytes(int64_t n, int32_t W, int32_t H);
 
 // Cell-ordered payload for compactly supported weights (from launch_cells).
 struct CellGeom;
@@ -204,6 +214,7 @@ struct FitPlan {
   size_t o_keys, o_keys2, o_perm, o_perm2, o_hist, o_cs, o_pts, o_vals_s;
   size_t o_tk, o_tk2, o_to, o_to2, o_th;
   size_t o_ts, o_tl, o_so, o_ssum;
+  size_t o_gtab, gtab_bytes;   // float64 Gaussian factor tables (gtab_bytes 0: none)
   int64_t order_slots;
   int64_t list_cap;       // entries of the per-tile point lists, at most
   size_t total;

@@ -125,11 +125,17 @@ def test_contour_invalid_arguments(lib, kwargs, needle):
 
 
 def test_fit_scratch_plan(lib):
-    """Host-only scratch plan: none for float64, staging for 16-bit paths,
-    more with the cell list."""
+    """Host-only scratch plan: the Gaussian factor tables for float64 (up to
+    the cap, none beyond it), staging for 16-bit paths, more with the cell
+    list."""
     from paper_1408_0677_amd import api
     grid = {"x0": 0.0, "y0": 0.0, "dx": 0.01, "dy": 0.01, "width": 100, "height": 100}
-    assert api.fit_scratch_bytes(1000, 4, grid, "f64") == 0
+    # 8 B x 1024 points (1000 padded to 64) x (112 columns + 112 rows)
+    assert api.fit_scratch_bytes(1000, 4, grid, "f64") == 8 * 1024 * (112 + 112)
+    # past 512 MiB of tables: generated per tile, no scratch
+    big = dict(grid, width=4096, height=4096)
+    assert api.fit_scratch_bytes(10 ** 6, 4, big, "f64") == 0
+    assert api.fit_scratch_bytes(1000, 4, grid, "f64", weight="invpow") > 0
     lp = api.fit_scratch_bytes(1000, 4, grid, "bf16")
     assert lp >= 4 * 1000 * 4
     wd = api.fit_scratch_bytes(1000, 4, grid, "bf16", weight="wendland", h=0.05)
