@@ -200,6 +200,37 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
   }
 }
 
+// The corner range of the whole wave chunk (NaN-free cells only).
+__device__ __forceinline__ void wave_range(const WaveCells& w, float* lo, float* hi) {
+  float a = w.lo, b = w.hi;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a = fminf(a, __shfl_xor(a, o, 64));
+    b = fmaxf(b, __shfl_xor(b, o, 64));
+  }
+  *lo = a;
+  *hi = b;
+}
+
+// Segments of one isovalue in a wave chunk: a cell has segments iff
+// min < iso <= max over its corners; it has two iff it is a saddle (case 5
+// or 10: diagonal corners on one side, the other diagonal on the other),
+// found on whole-wave masks.
+__device__ __forceinline__ int64_t wave_segments(const WaveCells& w, float iso) {
+  int64_t count = 0;
+#pragma unroll
+  for (int q = 0; q < kCellsPerLane; ++q) {
+    const uint64_t ok = __ballot(w.clo[q] < iso && iso <= w.chi[q]);
+    if (ok == 0) continue;
+    const Corners& c = w.c[q];
+    const uint64_t a0 = __ballot(c.v0 >= iso), a1 = __ballot(c.v1 >= iso);
+    const uint64_t a2 = __ballot(c.v2 >= iso), a3 = __ballot(c.v3 >= iso);
+    const uint64_t saddle = ok & ~(a0 ^ a2) & ~(a1 ^ a3) & (a0 ^ a1);
+    count += __popcll(ok) + __popcll(saddle);
+  }
+  return count;
+}
+
 __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(ContourParams p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -209,37 +240,44 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(Cont
   const float* f = p.fields + (int64_t)d * p.W * p.H;
   WaveCells w;
   load_wave_cells(p, f, chunk, lane, w);
-  // isovalues 64 at a time in one vector load, read back per iteration with
-  // a lane broadcast instead of a scalar memory load each
-  float isov = 0.0f;
-  for (int k = 0; k < p.n_iso; ++k) {
-    if ((k & 63) == 0) isov = (k + lane < p.n_iso) ? p.iso[d * p.n_iso + k + lane] : 0.0f;
-    const float iso = __builtin_bit_cast(
-        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), k & 63));
-    int64_t count = 0;
-    if (p.cases) {
+  if (p.cases) {
+    // with the case array every (isovalue, cell) is written: isovalues one
+    // at a time, 64 per vector load, broadcast per iteration
+    float isov = 0.0f;
+    for (int k = 0; k < p.n_iso; ++k) {
+      if ((k & 63) == 0) isov = (k + lane < p.n_iso) ? p.iso[d * p.n_iso + k + lane] : 0.0f;
+      const float iso = __builtin_bit_cast(
+          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), k & 63));
 #pragma unroll
       for (int q = 0; q < kCellsPerLane; ++q)
         if (w.in[q])
           p.cases[((int64_t)d * p.n_iso + k) * p.cells + w.cell[q]] =
               (uint8_t)cell_case(w.c[q], iso);
+      const int64_t count = wave_segments(w, iso);
+      if (lane == 0) p.counts[((int64_t)d * p.n_iso + k) * p.nchunk + chunk] = (int32_t)count;
     }
-    // a cell has segments iff min < iso <= max over its corners; it has two
-    // iff it is a saddle (case 5 or 10: diagonal corners on one side, the
-    // other diagonal on the other), found on whole-wave masks
-    if (__any(iso > w.lo && iso <= w.hi)) {
-#pragma unroll
-      for (int q = 0; q < kCellsPerLane; ++q) {
-        const uint64_t ok = __ballot(w.clo[q] < iso && iso <= w.chi[q]);
-        if (ok == 0) continue;
-        const Corners& c = w.c[q];
-        const uint64_t a0 = __ballot(c.v0 >= iso), a1 = __ballot(c.v1 >= iso);
-        const uint64_t a2 = __ballot(c.v2 >= iso), a3 = __ballot(c.v3 >= iso);
-        const uint64_t saddle = ok & ~(a0 ^ a2) & ~(a1 ^ a3) & (a0 ^ a1);
-        count += __popcll(ok) + __popcll(saddle);
-      }
+    return;
+  }
+  // Isovalues 64 at a time, one per lane: the wave's corner range picks the
+  // ones that can cross any of its cells (a ballot), only those are
+  // counted, and each lane stores its isovalue's count (zero for the rest)
+  // in one store.
+  float wlo, whi;
+  wave_range(w, &wlo, &whi);
+  for (int k0 = 0; k0 < p.n_iso; k0 += 64) {
+    const bool valid = k0 + lane < p.n_iso;
+    const float isov = valid ? p.iso[d * p.n_iso + k0 + lane] : 0.0f;
+    uint64_t act = __ballot(valid && isov > wlo && isov <= whi);
+    int32_t cnt = 0;
+    while (act) {
+      const int kk = __builtin_ctzll(act);
+      act &= act - 1;
+      const float iso = __builtin_bit_cast(
+          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), kk));
+      const int64_t count = wave_segments(w, iso);
+      if (lane == kk) cnt = (int32_t)count;
     }
-    if (lane == 0) p.counts[((int64_t)d * p.n_iso + k) * p.nchunk + chunk] = (int32_t)count;
+    if (valid) p.counts[((int64_t)d * p.n_iso + k0 + lane) * p.nchunk + chunk] = cnt;
   }
 }
 
@@ -315,6 +353,50 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t* sums, int64_t 
   if (t == 0) *total = tot;
 }
 
+// The segments of isovalue k of field d in one wave chunk, written from the
+// chunk's offset on in (cell, segment) order.
+__device__ __forceinline__ void emit_iso(const ContourParams& p, const WaveCells& w, int d, int k,
+                                         float iso, int64_t chunk, uint64_t below) {
+  const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
+  int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
+#pragma unroll
+  for (int q = 0; q < kCellsPerLane; ++q) {
+    // cells of this slot with one segment or more, and the saddles among
+    // them (two segments), as whole-wave masks, as in the count pass; the
+    // range is formed here rather than kept per cell, which would cost
+    // registers.  A slot no lane's cell crosses has nothing to write.
+    const Corners cq = w.c[q];
+    const bool has = cq.valid && fminf(fminf(cq.v0, cq.v1), fminf(cq.v2, cq.v3)) < iso &&
+                     iso <= fmaxf(fmaxf(cq.v0, cq.v1), fmaxf(cq.v2, cq.v3));
+    const uint64_t one = __ballot(has);
+    if (one == 0) continue;
+    const uint64_t m0 = __ballot(cq.v0 >= iso), m1 = __ballot(cq.v1 >= iso);
+    const uint64_t m2 = __ballot(cq.v2 >= iso), m3 = __ballot(cq.v3 >= iso);
+    const uint64_t two = one & ~(m0 ^ m2) & ~(m1 ^ m3) & (m0 ^ m1);
+    const int64_t base = run + __popcll(one & below) + __popcll(two & below);
+    run += __popcll(one) + __popcll(two);
+    if (!has) continue;
+    const int iq = w.i[q], jq = w.j[q];
+    int a0, a1, b0, b1;
+    const int ns = case_segments(cell_case(cq, iso), cq, iso, a0, a1, b0, b1);
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int64_t o = base + s2;
+      if (s2 < ns && o < p.capacity) {
+        float x0, y0, x1, y1;
+        edge_point(s2 ? b0 : a0, cq, iso, iq, jq, p.g, &x0, &y0);
+        edge_point(s2 ? b1 : a1, cq, iso, iq, jq, p.g, &x1, &y1);
+        reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
+        if (p.ids) {
+          p.ids[3 * o] = d;
+          p.ids[3 * o + 1] = k;
+          p.ids[3 * o + 2] = (int32_t)w.cell[q];
+        }
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(ContourParams p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -325,51 +407,20 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(Conto
   WaveCells w;
   load_wave_cells(p, f, chunk, lane, w);
   const uint64_t below = (1ull << lane) - 1ull;   // lanes before this one
-  // isovalues 64 at a time in one vector load, read back per iteration with
-  // a lane broadcast instead of a scalar memory load each
-  float isov = 0.0f;
-  for (int k = 0; k < p.n_iso; ++k) {
-    if ((k & 63) == 0) isov = (k + lane < p.n_iso) ? p.iso[d * p.n_iso + k + lane] : 0.0f;
-    const float iso = __builtin_bit_cast(
-        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), k & 63));
-    if (!__any(iso > w.lo && iso <= w.hi)) continue;
-    const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
-    int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
-#pragma unroll
-    for (int q = 0; q < kCellsPerLane; ++q) {
-      // cells of this slot with one segment or more, and the saddles among
-      // them (two segments), as whole-wave masks, as in the count pass; the
-      // range is formed here rather than kept per cell, which would cost
-      // registers.  A slot no lane's cell crosses has nothing to write.
-      const Corners cq = w.c[q];
-      const bool has = cq.valid && fminf(fminf(cq.v0, cq.v1), fminf(cq.v2, cq.v3)) < iso &&
-                       iso <= fmaxf(fmaxf(cq.v0, cq.v1), fmaxf(cq.v2, cq.v3));
-      const uint64_t one = __ballot(has);
-      if (one == 0) continue;
-      const uint64_t m0 = __ballot(cq.v0 >= iso), m1 = __ballot(cq.v1 >= iso);
-      const uint64_t m2 = __ballot(cq.v2 >= iso), m3 = __ballot(cq.v3 >= iso);
-      const uint64_t two = one & ~(m0 ^ m2) & ~(m1 ^ m3) & (m0 ^ m1);
-      const int64_t base = run + __popcll(one & below) + __popcll(two & below);
-      run += __popcll(one) + __popcll(two);
-      if (!has) continue;
-      const int iq = w.i[q], jq = w.j[q];
-      int a0, a1, b0, b1;
-      const int ns = case_segments(cell_case(cq, iso), cq, iso, a0, a1, b0, b1);
-#pragma unroll
-      for (int s2 = 0; s2 < 2; ++s2) {
-        const int64_t o = base + s2;
-        if (s2 < ns && o < p.capacity) {
-          float x0, y0, x1, y1;
-          edge_point(s2 ? b0 : a0, cq, iso, iq, jq, p.g, &x0, &y0);
-          edge_point(s2 ? b1 : a1, cq, iso, iq, jq, p.g, &x1, &y1);
-          reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
-          if (p.ids) {
-            p.ids[3 * o] = d;
-            p.ids[3 * o + 1] = k;
-            p.ids[3 * o + 2] = (int32_t)w.cell[q];
-          }
-        }
-      }
+  // isovalues 64 at a time, one per lane; only those inside the wave's
+  // corner range can have segments here (as in the count pass)
+  float wlo, whi;
+  wave_range(w, &wlo, &whi);
+  for (int k0 = 0; k0 < p.n_iso; k0 += 64) {
+    const bool valid = k0 + lane < p.n_iso;
+    const float isov = valid ? p.iso[d * p.n_iso + k0 + lane] : 0.0f;
+    uint64_t act = __ballot(valid && isov > wlo && isov <= whi);
+    while (act) {
+      const int kk = __builtin_ctzll(act);
+      act &= act - 1;
+      const float iso = __builtin_bit_cast(
+          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), kk));
+      emit_iso(p, w, d, k0 + kk, iso, chunk, below);
     }
   }
 }

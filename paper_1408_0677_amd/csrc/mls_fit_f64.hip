@@ -95,9 +95,10 @@ struct F64Params {
 };
 
 // Weight modes of the kernel: the Gaussian with per-tile factors from a
-// stepping recurrence, the inverse-distance weight per pair, the Gaussian
-// with factors copied from per-launch tables.
-constexpr int WM_GAUSS = 0, WM_INV = 1, WM_TABLE = 2;
+// stepping recurrence, the inverse-distance weight per pair (any exponent,
+// or alpha = 1 and alpha = 2 through a reciprocal), the Gaussian with
+// factors copied from per-launch tables.
+constexpr int WM_GAUSS = 0, WM_INV = 1, WM_TABLE = 2, WM_INV1 = 3, WM_INV2 = 4;
 
 template <int DEG, int NT, int R>
 struct F64Layout {
@@ -149,6 +150,21 @@ __device__ __forceinline__ double invpow_weight(double ox, double oy, double alp
   return ldexp((double)exp2f((float)(e - ip)), (int)ip);
 }
 
+// The same weight for alpha = 1 and alpha = 2: (r^2)^-1 and its square from
+// the hardware reciprocal refined by two Newton steps (correct to rounding,
+// where the general form carries float32's 1e-7), about half the vector
+// instructions.  The clamps keep r^2 = 0 finite, as the general form does.
+template <int ALPHA>
+__device__ __forceinline__ double invpow_weight_int(double ox, double oy) {
+  const double r2 = ox * ox + oy * oy;
+  if (!(r2 < 1e300)) return 0.0;
+  const double x = fmax(r2, ALPHA == 1 ? 1e-300 : 0x1p-500);
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return ALPHA == 1 ? r : r * r;
+}
+
 __device__ __forceinline__ void read4(const double* src, double* dst) {
   const double2* v = reinterpret_cast<const double2*>(src);
   const double2 lo = v[0], hi = v[1];
@@ -164,7 +180,7 @@ __device__ __forceinline__ void read4(const double* src, double* dst) {
 // rigid map of 2-vector values from the linear moments.
 template <int DEG, int NT, int R, int WM, int EPI>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
-  constexpr bool INV = WM == WM_INV;
+  constexpr bool INV = WM == WM_INV || WM == WM_INV1 || WM == WM_INV2;
   using L = F64Layout<DEG, NT, R>;
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
   constexpr int nmom = DEG == 0 ? 1 : (DEG == 1 ? 6 : 15);
@@ -384,7 +400,10 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-          const double a = INV ? invpow_weight(ax[j], ay[t][j], p.alpha) : ax[j] * ay[t][j];
+          const double a = WM == WM_INV1   ? invpow_weight_int<1>(ax[j], ay[t][j])
+                           : WM == WM_INV2 ? invpow_weight_int<2>(ax[j], ay[t][j])
+                           : INV           ? invpow_weight(ax[j], ay[t][j], p.alpha)
+                                           : ax[j] * ay[t][j];
 #pragma unroll
           for (int q = 0; q < NT; ++q)
             acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[q][j], acc[t][q], 0, 0, 0);
@@ -479,6 +498,11 @@ hipError_t launch_nt(const F64Params& p, hipStream_t s) {
 
 template <int DEG, int WM>
 hipError_t launch_deg(const F64Params& p, int nt, hipStream_t s) {
+  if constexpr (WM == WM_INV1 || WM == WM_INV2) {
+    // the reciprocal forms serve one and two feature tiles, where the
+    // weight is most of the vector work per matrix instruction
+    return nt == 1 ? launch_nt<DEG, 1, WM>(p, s) : launch_nt<DEG, 2, WM>(p, s);
+  }
   switch (nt) {
     case 1: return launch_nt<DEG, 1, WM>(p, s);
     case 2: return launch_nt<DEG, 2, WM>(p, s);
@@ -548,7 +572,11 @@ hipError_t launch_fit_f64(const FitArgs& a, hipStream_t stream) {
   p.deg_out = a.deg_out;
   p.grads = a.grads;
   p.rigid = a.rigid;
-  if (a.wkind == 2) return launch_kind<WM_INV>(p, a.degree, nt, stream);   // inverse distance
+  if (a.wkind == 2) {   // inverse distance
+    if (nt <= 2 && a.alpha == 1.0) return launch_kind<WM_INV1>(p, a.degree, nt, stream);
+    if (nt <= 2 && a.alpha == 2.0) return launch_kind<WM_INV2>(p, a.degree, nt, stream);
+    return launch_kind<WM_INV>(p, a.degree, nt, stream);
+  }
   if (!a.gtab) return launch_kind<WM_GAUSS>(p, a.degree, nt, stream);
   p.tab = a.gtab;
   p.tab_n = f64_table_points(a.n);

@@ -138,6 +138,28 @@ def test_c2_full_size_sampled(torch_dev, oracle):
     assert st["pass_set"] > 0.5 * st["nodes"]
 
 
+@pytest.mark.parametrize("basis", ["linear", "quadratic"])
+def test_factor_generation_beyond_the_table_cap(torch_dev, oracle, basis):
+    """Where the Gaussian factor tables would pass their 512 MiB cap (here
+    70,000 points on a 512^2 grid: 573 MB) the kernel generates the factors
+    per tile; checked on sampled nodes and a window like the table path."""
+    from paper_1408_0677_amd import api, workloads as wl
+    w = wl.c2(grid_side=512, n=70_000)
+    assert api.fit_scratch_bytes(w.n, w.d, w.grid, "f64") == 0    # no tables
+    note(f"case f64 without tables {basis} n={w.n}")
+    h = 0.01 if basis == "linear" else 0.02    # most nodes well conditioned
+    F, deg = gpu_fit(torch_dev, w.points, w.values, w.grid, basis=basis, h=h)
+    W = w.grid["width"]
+    rng = np.random.default_rng(9)
+    win = (np.arange(200, 216)[:, None] * W + np.arange(100, 116)[None, :]).ravel()
+    pix = np.unique(np.concatenate([rng.choice(W * W, 300, replace=False), win]))
+    of, od, dm = oracle.fit_grid(w.points, w.values, w.grid, basis=basis, h=h, pixels=pix)
+    st = compare(F.reshape(w.d, -1)[:, pix], deg.ravel()[pix], of, od, dm, w.values)
+    note(str({k: v for k, v in st.items() if k != "per_field_max_pass"}))
+    check(st)
+    assert st["pass_set"] > 0.5 * st["nodes"]
+
+
 def test_deterministic(torch_dev):
     from paper_1408_0677_amd import workloads as wl
     w = wl.c2(grid_side=256)

@@ -37,7 +37,7 @@ def gpu_fit(torch, pts, vals, grid, **kw):
     return f.cpu().numpy(), d.cpu().numpy()
 
 
-@pytest.mark.parametrize("alpha", [0.5, 1.0, 1.5])
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 1.5, 2.0])
 @pytest.mark.parametrize("basis", ["constant", "linear", "quadratic"])
 def test_invpow_matches_oracle(torch_dev, oracle, basis, alpha):
     from paper_1408_0677_amd import workloads as wl
