@@ -652,7 +652,7 @@ struct ShapeLayout {
   static constexpr int kRawIt = (kRawFloats + kProd - 1) / kProd;
   static constexpr int kFeatB = kFeatRows * KSH * 2;
   static constexpr int kTabB = (kCols + kRows) * KSF * 4;
-  static constexpr int kBasB = m * KSF * 4;
+  static constexpr int kBasB = 3 * KSF * 4;              // 1, u_x, u_y per point
   static constexpr int kRawB = kRawFloats * 4;
   static constexpr int kFeat0 = 0;
   static constexpr int kTab0 = kFeat0 + 2 * kFeatB;
@@ -764,8 +764,9 @@ __device__ __forceinline__ void point_monomials(const LPParams& p, float x, floa
 }
 
 // Producer, pass 1: tables and the moment monomials (S1 terms, rows
-// s * 16 + j).  Pass 2: tables, the basis rows b_j of the chunk's points
-// (float32, row j of `bas`), and the attribute terms (rows s * kDs + d).
+// s * 16 + j).  Pass 2: tables, the linear basis rows 1, u_x, u_y of the
+// chunk's points (float32, rows 0-2 of `bas`; zero past the reach), and
+// the attribute terms (rows s * kDs + d).
 // A thread owns two consecutive points and one eighth of the rows.
 template <int DEG, int NTV, int S1, bool PASS2>
 __device__ __forceinline__ void shape_chunk(const LPParams& p, const float* raw, int kn, int nv,
@@ -786,7 +787,7 @@ __device__ __forceinline__ void shape_chunk(const LPParams& p, const float* raw,
     return;
   }
 #pragma unroll
-  for (int j = 0; j < L::m; ++j)
+  for (int j = 0; j < 3; ++j)   // 1, u_x, u_y (the matrix waves form the rest)
     if ((j & 7) == g) {
       bas[j * KSF + k0] = mo0[j];
       bas[j * KSF + k0 + 1] = mo1[j];
@@ -987,15 +988,21 @@ __global__ __launch_bounds__(kThreads) void fit_shape_kernel(LPParams p) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int k = ks + k8 + q;
-            float bj[m];
-#pragma unroll
-            for (int j = 0; j < m; ++j) bj[j] = bs[j * KSF + k];
+            // b = (1, u_x, u_y[, u_x^2, u_x u_y, u_y^2]), zero past the reach:
+            // the quadratic terms follow from the linear ones (Horner), so a
+            // point needs three values, not six
+            const float b0 = bs[k], b1 = bs[KSF + k], b2 = bs[2 * KSF + k];
             const float wxq = gx[i * KSF + k];
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-              float sh = yv[t][0] * bj[0];
-#pragma unroll
-              for (int j = 1; j < m; ++j) sh = fmaf(yv[t][j], bj[j], sh);
+              float sh;
+              if (DEG == 1) {
+                sh = fmaf(yv[t][2], b2, fmaf(yv[t][1], b1, yv[t][0] * b0));
+              } else {
+                const float s1 = fmaf(yv[t][3], b1, fmaf(yv[t][4], b2, yv[t][1]));
+                const float s2 = fmaf(yv[t][5], b2, yv[t][2]);
+                sh = fmaf(b1, s1, fmaf(b2, s2, yv[t][0] * b0));
+              }
               const float w = (wxq * gy[(wave * R + t) * KSF + k]) * sh;
               const __bf16 hw = (__bf16)w;
               ahi[t][q] = hw;
