@@ -58,8 +58,12 @@ namespace mls {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 
 #ifndef MLS_LP_MMA_WAVES
 #define MLS_LP_MMA_WAVES 8
@@ -78,6 +82,52 @@ constexpr int kDsCap = 40;                 // attributes per slab at most
 template <typename T> struct Vec8;
 template <> struct Vec8<__bf16> { typedef bf16x8 type; };
 template <> struct Vec8<_Float16> { typedef halfx8 type; };
+
+// Two float32 values rounded (nearest-even) to a packed pair of 16-bit
+// numbers, first value in the low half: one packed conversion per pair.
+template <typename T> __device__ __forceinline__ uint32_t pack2(float a, float b);
+template <> __device__ __forceinline__ uint32_t pack2<__bf16>(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){a, b}, bf16x2));
+}
+template <> __device__ __forceinline__ uint32_t pack2<_Float16>(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){a, b}, halfx2));
+}
+
+// The same, also returning what the rounding left of each value (exact in
+// float32): one term of a multi-term 16-bit expansion.
+template <typename T>
+__device__ __forceinline__ uint32_t pack2_rest(float a, float b, float& ra, float& rb);
+template <>
+__device__ __forceinline__ uint32_t pack2_rest<__bf16>(float a, float b, float& ra, float& rb) {
+  const uint32_t p = pack2<__bf16>(a, b);
+  ra = a - __builtin_bit_cast(float, p << 16);
+  rb = b - __builtin_bit_cast(float, p & 0xFFFF0000u);
+  return p;
+}
+template <>
+__device__ __forceinline__ uint32_t pack2_rest<_Float16>(float a, float b, float& ra, float& rb) {
+  const uint32_t p = pack2<_Float16>(a, b);
+  const floatx2 back = __builtin_convertvector(__builtin_bit_cast(halfx2, p), floatx2);
+  ra = a - back.x;
+  rb = b - back.y;
+  return p;
+}
+
+// Eight float32 weights as the hi + lo pair of 16-bit operands: hi is the
+// rounding of w, lo the rounding of what hi leaves.
+template <typename T>
+__device__ __forceinline__ void split_weights(const float (&w)[8], typename Vec8<T>::type& hi,
+                                              typename Vec8<T>::type& lo) {
+  u32x4 h, l;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    float r0, r1;
+    h[p] = pack2_rest<T>(w[2 * p], w[2 * p + 1], r0, r1);
+    l[p] = pack2<T>(r0, r1);
+  }
+  hi = __builtin_bit_cast(typename Vec8<T>::type, h);
+  lo = __builtin_bit_cast(typename Vec8<T>::type, l);
+}
 
 // Common factor applied to every weight before it is rounded to the 16-bit
 // operand.  float16 has a 5-bit exponent: a Gaussian weight below 6e-5
@@ -179,11 +229,13 @@ __device__ __forceinline__ double node_offset_yd(const LPParams& p, int r0, int 
 // sequence, which costs eight more instructions per pair: the weight is
 // carried as hi + lo bfloat16 terms, about 17 bits, and any rounding of it
 // is common to every feature of the pair.
+// 1 - s is clamped at 0 (a clamp bit of the subtraction), which makes the
+// weight 0 from s = 1 on.
 __device__ __forceinline__ float wendland_c2(float s2) {
   const float s = __builtin_amdgcn_sqrtf(s2);
-  const float t = 1.0f - s;
+  const float t = __builtin_amdgcn_fmed3f(1.0f - s, 0.0f, 1.0f);
   const float t2 = t * t;
-  return s < 1.0f ? t2 * t2 * (4.0f * s + 1.0f) : 0.0f;
+  return t2 * t2 * (4.0f * s + 1.0f);
 }
 
 // Producer: global -> registers for one raw chunk.
@@ -255,7 +307,6 @@ __device__ __forceinline__ void make_chunk(const LPParams& p, const float* raw, 
                                            float* tab, T* G, int pt, const float (&toff)[kTabIt],
                                            float cxr, float cyr) {
   using L = LPLayout<DEG, NTS, S, T>;
-  typedef T T2 __attribute__((ext_vector_type(2)));
   constexpr int m = L::m, nmom = L::nmom;
   const float* rx = raw;
   const float* ry = raw + KT;
@@ -310,13 +361,16 @@ __device__ __forceinline__ void make_chunk(const LPParams& p, const float* raw, 
     T* dst = G + (size_t)j * KSH + k0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const T t0 = (T)v0, t1 = (T)v1;
-      v0 -= (float)t0;
-      v1 -= (float)t1;
-      T2 pr;
-      pr.x = t0;
-      pr.y = t1;
-      *(T2*)(dst + (size_t)s * L::kFP * KSH) = pr;
+      uint32_t pr;
+      if (s + 1 < S) {
+        float r0, r1;
+        pr = pack2_rest<T>(v0, v1, r0, r1);
+        v0 = r0;
+        v1 = r1;
+      } else {
+        pr = pack2<T>(v0, v1);
+      }
+      *(uint32_t*)(dst + (size_t)s * L::kFP * KSH) = pr;
     }
   };
 #pragma unroll
@@ -415,23 +469,27 @@ __device__ __forceinline__ void lp_tile(const LPParams& p, int block, char* lds_
 #pragma unroll
         for (int q = 0; q < 8; ++q) wx[q] = gx[i * KSF + ks + k8 + q];
         vec8 ahi[R], alo[R];
-        bool nz = false;
+        float smin = 4.0f;   // Wendland: the smallest u^2 among this lane's pairs
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const float* gyr = gy + (wave * R + t) * KSF + ks + k8;
+          float w[8];
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            const float w =
-                WEND ? wendland_c2(wx[q] + gyr[q]) * WeightGain<T>::value : wx[q] * gyr[q];
-            nz = nz || w != 0.0f;
-            const T hw = (T)w;
-            ahi[t][q] = hw;
-            alo[t][q] = (T)(w - (float)hw);
+            if (WEND) {
+              const float s2 = wx[q] + gyr[q];
+              smin = fminf(smin, s2);
+              w[q] = wendland_c2(s2) * WeightGain<T>::value;
+            } else {
+              w[q] = wx[q] * gyr[q];
+            }
           }
+          split_weights<T>(w, ahi[t], alo[t]);
         }
         // compact support: a k-step in which no pair of this wave's nodes
-        // has weight adds nothing; its matrix instructions are skipped
-        if (WEND && !__any(nz)) continue;
+        // lies inside the support (all weights zero) adds nothing; its
+        // matrix instructions are skipped
+        if (WEND && !__any(smin < 1.0f)) continue;
 #pragma unroll
         for (int q = 0; q < NTS; ++q) {
 #pragma unroll
@@ -723,16 +781,18 @@ __device__ __forceinline__ void gauss_tables(const LPParams& p, const float* raw
 // dst + s * stride.
 template <int S>
 __device__ __forceinline__ void emit_terms(__bf16* dst, size_t stride, float v0, float v1) {
-  typedef __bf16 B2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const __bf16 t0 = (__bf16)v0, t1 = (__bf16)v1;
-    v0 -= (float)t0;
-    v1 -= (float)t1;
-    B2 pr;
-    pr.x = t0;
-    pr.y = t1;
-    *(B2*)(dst + (size_t)s * stride) = pr;
+    uint32_t pr;
+    if (s + 1 < S) {
+      float r0, r1;
+      pr = pack2_rest<__bf16>(v0, v1, r0, r1);
+      v0 = r0;
+      v1 = r1;
+    } else {
+      pr = pack2<__bf16>(v0, v1);
+    }
+    *(uint32_t*)(dst + (size_t)s * stride) = pr;
   }
 }
 
@@ -871,13 +931,10 @@ __global__ __launch_bounds__(kThreads) void fit_shape_kernel(LPParams p) {
 #pragma unroll
           for (int t = 0; t < R; ++t) {
             const float* gyr = gy + (wave * R + t) * KSF + ks + k8;
+            float w[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const float w = wx[q] * gyr[q];
-              const __bf16 hw = (__bf16)w;
-              ahi[t][q] = hw;
-              alo[t][q] = (__bf16)(w - (float)hw);
-            }
+            for (int q = 0; q < 8; ++q) w[q] = wx[q] * gyr[q];
+            split_weights<__bf16>(w, ahi[t], alo[t]);
           }
 #pragma unroll
           for (int s = 0; s < S1; ++s) {
@@ -983,31 +1040,45 @@ __global__ __launch_bounds__(kThreads) void fit_shape_kernel(LPParams p) {
 #pragma unroll
         for (int ks = 0; ks < KT; ks += 32) {
           bf16x8 ahi[R], alo[R];
-          // one point at a time: its basis values and column factor, then
-          // the effective weight of each of the lane's nodes
+          u32x4 hv[R], lv[R];
+          // two points at a time: their basis values and column factors,
+          // then the effective weight of each of the lane's nodes, split
+          // hi + lo with one packed conversion per pair
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int k = ks + k8 + q;
-            // b = (1, u_x, u_y[, u_x^2, u_x u_y, u_y^2]), zero past the reach:
-            // the quadratic terms follow from the linear ones (Horner), so a
-            // point needs three values, not six
-            const float b0 = bs[k], b1 = bs[KSF + k], b2 = bs[2 * KSF + k];
-            const float wxq = gx[i * KSF + k];
+          for (int q = 0; q < 8; q += 2) {
+            float w[R][2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const int k = ks + k8 + q + e;
+              // b = (1, u_x, u_y[, u_x^2, u_x u_y, u_y^2]), zero past the
+              // reach: the quadratic terms follow from the linear ones
+              // (Horner), so a point needs three values, not six
+              const float b0 = bs[k], b1 = bs[KSF + k], b2 = bs[2 * KSF + k];
+              const float wxq = gx[i * KSF + k];
+#pragma unroll
+              for (int t = 0; t < R; ++t) {
+                float sh;
+                if (DEG == 1) {
+                  sh = fmaf(yv[t][2], b2, fmaf(yv[t][1], b1, yv[t][0] * b0));
+                } else {
+                  const float s1 = fmaf(yv[t][3], b1, fmaf(yv[t][4], b2, yv[t][1]));
+                  const float s2 = fmaf(yv[t][5], b2, yv[t][2]);
+                  sh = fmaf(b1, s1, fmaf(b2, s2, yv[t][0] * b0));
+                }
+                w[t][e] = (wxq * gy[(wave * R + t) * KSF + k]) * sh;
+              }
+            }
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-              float sh;
-              if (DEG == 1) {
-                sh = fmaf(yv[t][2], b2, fmaf(yv[t][1], b1, yv[t][0] * b0));
-              } else {
-                const float s1 = fmaf(yv[t][3], b1, fmaf(yv[t][4], b2, yv[t][1]));
-                const float s2 = fmaf(yv[t][5], b2, yv[t][2]);
-                sh = fmaf(b1, s1, fmaf(b2, s2, yv[t][0] * b0));
-              }
-              const float w = (wxq * gy[(wave * R + t) * KSF + k]) * sh;
-              const __bf16 hw = (__bf16)w;
-              ahi[t][q] = hw;
-              alo[t][q] = (__bf16)(w - (float)hw);
+              float r0, r1;
+              hv[t][q / 2] = pack2_rest<__bf16>(w[t][0], w[t][1], r0, r1);
+              lv[t][q / 2] = pack2<__bf16>(r0, r1);
             }
+          }
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            ahi[t] = __builtin_bit_cast(bf16x8, hv[t]);
+            alo[t] = __builtin_bit_cast(bf16x8, lv[t]);
           }
 #pragma unroll
           for (int q = 0; q < NTV; ++q) {

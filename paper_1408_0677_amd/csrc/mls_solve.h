@@ -54,12 +54,13 @@ __device__ __forceinline__ double shift_entry(int r, int c, double ex, double ey
 // equilibrated matrix S M_p' S is factored (L, every pivot >= tau) until a
 // degree is accepted.  Fills the factor and y = T'^T M_p'^{-1} e_0, the
 // tile-frame coefficients of the node's shape function: the fitted value
-// is y^T R_t.  Returns the accepted degree, or 255 when the weight sum
+// is y^T R_t.  The reciprocal of each diagonal entry of L is kept (r), so
+// the triangular solves multiply instead of dividing.  Returns the accepted degree, or 255 when the weight sum
 // (divided by wscale) is below the floor or no degree is accepted.
 template <int DEG>
 struct Ladder {
   static constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
-  double T[m][m], L[m][m], s[m], q[m], w[m], y[m];
+  double T[m][m], L[m][m], r[m], s[m], q[m], w[m], y[m];
   int mk;
 };
 
@@ -124,6 +125,7 @@ __device__ __forceinline__ int ladder_solve(const Acc* g, double ex, double ey, 
       }
       lad.L[j][j] = sqrt(piv);
       const double inv = 1.0 / lad.L[j][j];
+      lad.r[j] = inv;
 #pragma unroll
       for (int r = j + 1; r < m; ++r) {
         if (r >= mk) continue;
@@ -141,7 +143,7 @@ __device__ __forceinline__ int ladder_solve(const Acc* g, double ex, double ey, 
       double v = r == 0 ? lad.s[0] : 0.0;
 #pragma unroll
       for (int c = 0; c < r; ++c) v -= lad.L[r][c] * lad.q[c];
-      lad.q[r] = v / lad.L[r][r];
+      lad.q[r] = v * lad.r[r];
     }
 #pragma unroll
     for (int r = m - 1; r >= 0; --r) {
@@ -150,7 +152,7 @@ __device__ __forceinline__ int ladder_solve(const Acc* g, double ex, double ey, 
 #pragma unroll
       for (int c = r + 1; c < m; ++c)
         if (c < mk) v -= lad.L[c][r] * lad.w[c];
-      lad.w[r] = v / lad.L[r][r];
+      lad.w[r] = v * lad.r[r];
     }
     // y = T'^T z over the accepted rows
 #pragma unroll
@@ -208,7 +210,7 @@ __device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, do
           double v = r == a ? lad.s[r] : 0.0;
 #pragma unroll
           for (int c = 0; c < r; ++c) v -= lad.L[r][c] * lad.q[c];
-          lad.q[r] = v / lad.L[r][r];
+          lad.q[r] = v * lad.r[r];
         }
 #pragma unroll
         for (int r = m - 1; r >= 0; --r) {
@@ -217,7 +219,7 @@ __device__ __forceinline__ uint8_t solve_node(const Acc* g, int D, double ex, do
 #pragma unroll
           for (int c = r + 1; c < m; ++c)
             if (c < mk) v -= lad.L[c][r] * lad.w[c];
-          lad.w[r] = v / lad.L[r][r];
+          lad.w[r] = v * lad.r[r];
         }
 #pragma unroll
         for (int c = 0; c < m; ++c) {

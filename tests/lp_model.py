@@ -37,7 +37,7 @@ def bf16(x):
 
 
 def fit_tiles(points, values, grid, h, tiles, terms=3, features="bf16", weight="split",
-              accumulate="f32"):
+              accumulate="f32", rhs_terms=None):
     """Quadratic-basis Gaussian MLS fields on the nodes of the given 16 x 16
     tiles, under the chosen arithmetic:
 
@@ -45,8 +45,11 @@ def fit_tiles(points, values, grid, h, tiles, terms=3, features="bf16", weight="
                 "f32" (float32 features), "f64" (exact features)
     weight      "split" (hi + lo, lo times every term but the last),
                 "lo1" (hi + lo, lo times the first term only),
+                "hi" (the bfloat16 rounding of the weight alone, every term),
                 "exact" (the float32 weight, or float64 with features="f64")
     accumulate  "f32" (one float32 rounding per step and product) or "f64"
+    rhs_terms   with features="bf16": the basis x attribute columns keep only
+                their first rhs_terms terms (default: all `terms`)
 
     Returns fields (D, H, W), NaN outside the tiles.
     """
@@ -98,6 +101,10 @@ def fit_tiles(points, values, grid, h, tiles, terms=3, features="bf16", weight="
                 q = bf16(rest)
                 terms_g.append(q)
                 rest = (rest - q).astype(np.float32)
+            if rhs_terms is not None:
+                for s in range(rhs_terms, terms):
+                    terms_g[s] = terms_g[s].copy()
+                    terms_g[s][:, 15:] = 0.0
         else:
             terms_g = [G]
         if weight == "exact":
