@@ -22,8 +22,9 @@
 //           [min, max] corner range is skipped with one wave-wide test;
 //   scan:   exclusive scan of the counts in (field, iso, chunk) order;
 //   emit:   recompute; a segment's slot is the chunk's scanned offset plus
-//           the ballot prefix of the cells before it, then write segments
-//           and ids.
+//           the ballot prefix of the cells before it; crossed cells are
+//           queued in LDS and their segments and ids written one cell per
+//           lane.
 // Reading the fields is one pass of HBM traffic per kernel; with many
 // isovalues the per-(cell, iso) tests dominate (vector ALU).
 #include <hip/hip_runtime.h>
@@ -188,6 +189,9 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
     v[q][2] = f[at[q] + p.W + 1];
     v[q][3] = f[at[q] + p.W];
   }
+  // keep the scheduler from moving a use of the first loads above the
+  // later loads (which would wait for the first before issuing the rest)
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int q = 0; q < kCellsPerLane; ++q) {
     Corners c{v[q][0], v[q][1], v[q][2], v[q][3], false};
@@ -238,6 +242,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(Cont
   const int64_t chunk = (blk % p.bpf) * kWavesPerBlock + wave;
   if (chunk >= p.nchunk) return;   // whole wave; the kernel has no barrier
   const float* f = p.fields + (int64_t)d * p.W * p.H;
+  // the first 64 isovalues, loaded in flight with the corner loads
+  const float isov0 = lane < p.n_iso ? p.iso[d * p.n_iso + lane] : 0.0f;
   WaveCells w;
   load_wave_cells(p, f, chunk, lane, w);
   if (p.cases) {
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void contour_count_kernel(Cont
   wave_range(w, &wlo, &whi);
   for (int k0 = 0; k0 < p.n_iso; k0 += 64) {
     const bool valid = k0 + lane < p.n_iso;
-    const float isov = valid ? p.iso[d * p.n_iso + k0 + lane] : 0.0f;
+    const float isov = k0 == 0 ? isov0 : (valid ? p.iso[d * p.n_iso + k0 + lane] : 0.0f);
     uint64_t act = __ballot(valid && isov > wlo && isov <= whi);
     int32_t cnt = 0;
     while (act) {
@@ -353,76 +359,160 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t* sums, int64_t 
   if (t == 0) *total = tot;
 }
 
-// The segments of isovalue k of field d in one wave chunk, written from the
-// chunk's offset on in (cell, segment) order.
-__device__ __forceinline__ void emit_iso(const ContourParams& p, const WaveCells& w, int d, int k,
-                                         float iso, int64_t chunk, uint64_t below) {
-  const int64_t slot = ((int64_t)d * p.n_iso + k) * p.nchunk + chunk;
-  int64_t run = p.offsets[slot] + p.tile_prefix[slot / kScanTile];
+// Emission is done in two steps so that the case and edge work runs on full
+// waves: a contour crosses only a few of a chunk's 256 cells per isovalue,
+// and working through them where they lie would keep one or two lanes of 64
+// busy.  Per isovalue, each crossed cell's output slot is found (the
+// chunk's scanned offset plus the ballot prefix of the cells before it) and
+// the cell is queued in LDS with its corners and slot; whenever the queue
+// might not take another 64 cells, and at the end, the wave drains it, one
+// queued cell per lane.  The queue is private to its wave (no barriers).
+constexpr int kQueue = 128;   // queued cells per wave
+
+struct QueuedCell {
+  float4 c;        // corners v0..v3
+  int64_t o;       // output slot of the cell's first segment
+  int32_t k;       // isovalue index
+  int32_t slot;    // cell within the chunk (q * 64 + lane)
+  int32_t i, j;    // row and column
+};
+
+struct EmitLds {
+  QueuedCell q[kWavesPerBlock][kQueue];
+};
+
+// Orders this wave's LDS writes before the reads that follow (LDS requests
+// of one wave complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Write the segments of the n queued cells, one cell per lane.
+__device__ __forceinline__ void drain_queue(const ContourParams& p, EmitLds& L, int wave, int d,
+                                            int64_t chunk, int n, int lane) {
+  wave_lds_sync();
+  for (int e = lane; e < n; e += 64) {
+    const QueuedCell qc = L.q[wave][e];
+    const Corners cq{qc.c.x, qc.c.y, qc.c.z, qc.c.w, true};
+    const float iso = p.iso[d * p.n_iso + qc.k];
+    int a0, a1, b0, b1;
+    const int ns = case_segments(cell_case(cq, iso), cq, iso, a0, a1, b0, b1);
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int64_t o = qc.o + s2;
+      if (s2 < ns && o < p.capacity) {
+        float x0, y0, x1, y1;
+        edge_point(s2 ? b0 : a0, cq, iso, qc.i, qc.j, p.g, &x0, &y0);
+        edge_point(s2 ? b1 : a1, cq, iso, qc.i, qc.j, p.g, &x1, &y1);
+        reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
+        if (p.ids) {
+          p.ids[3 * o] = d;
+          p.ids[3 * o + 1] = qc.k;
+          p.ids[3 * o + 2] = (int32_t)(chunk * kCellsPerWave + qc.slot);
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+// Queue the crossed cells of isovalue k of field d in one wave chunk with
+// the slots their segments take, in (cell, segment) order from the chunk's
+// offset `run` on.  `nq` is the wave's queue length (the same in every
+// lane).
+__device__ __forceinline__ void queue_iso(const ContourParams& p, const WaveCells& w, EmitLds& L,
+                                          int wave, int d, int k, float iso, int64_t chunk,
+                                          int64_t run, uint64_t below, int lane, int& nq) {
 #pragma unroll
   for (int q = 0; q < kCellsPerLane; ++q) {
-    // cells of this slot with one segment or more, and the saddles among
-    // them (two segments), as whole-wave masks, as in the count pass; the
-    // range is formed here rather than kept per cell, which would cost
-    // registers.  A slot no lane's cell crosses has nothing to write.
+    // cells of this group with one segment or more, and the saddles among
+    // them (two segments), as whole-wave masks, as in the count pass.  A
+    // group no lane's cell crosses has nothing to queue.
     const Corners cq = w.c[q];
-    const bool has = cq.valid && fminf(fminf(cq.v0, cq.v1), fminf(cq.v2, cq.v3)) < iso &&
-                     iso <= fmaxf(fmaxf(cq.v0, cq.v1), fmaxf(cq.v2, cq.v3));
+    const bool has = w.clo[q] < iso && iso <= w.chi[q];
     const uint64_t one = __ballot(has);
     if (one == 0) continue;
     const uint64_t m0 = __ballot(cq.v0 >= iso), m1 = __ballot(cq.v1 >= iso);
     const uint64_t m2 = __ballot(cq.v2 >= iso), m3 = __ballot(cq.v3 >= iso);
     const uint64_t two = one & ~(m0 ^ m2) & ~(m1 ^ m3) & (m0 ^ m1);
-    const int64_t base = run + __popcll(one & below) + __popcll(two & below);
-    run += __popcll(one) + __popcll(two);
-    if (!has) continue;
-    const int iq = w.i[q], jq = w.j[q];
-    int a0, a1, b0, b1;
-    const int ns = case_segments(cell_case(cq, iso), cq, iso, a0, a1, b0, b1);
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int64_t o = base + s2;
-      if (s2 < ns && o < p.capacity) {
-        float x0, y0, x1, y1;
-        edge_point(s2 ? b0 : a0, cq, iso, iq, jq, p.g, &x0, &y0);
-        edge_point(s2 ? b1 : a1, cq, iso, iq, jq, p.g, &x1, &y1);
-        reinterpret_cast<float4*>(p.segs)[o] = make_float4(x0, y0, x1, y1);
-        if (p.ids) {
-          p.ids[3 * o] = d;
-          p.ids[3 * o + 1] = k;
-          p.ids[3 * o + 2] = (int32_t)w.cell[q];
-        }
-      }
+    if (nq > kQueue - 64) {
+      drain_queue(p, L, wave, d, chunk, nq, lane);
+      nq = 0;
     }
+    if (has) {
+      QueuedCell qc;
+      qc.c = make_float4(cq.v0, cq.v1, cq.v2, cq.v3);
+      qc.o = run + __popcll(one & below) + __popcll(two & below);
+      qc.k = k;
+      qc.slot = q * 64 + lane;
+      qc.i = w.i[q];
+      qc.j = w.j[q];
+      L.q[wave][nq + __popcll(one & below)] = qc;
+    }
+    nq += __popcll(one);
+    run += __popcll(one) + __popcll(two);
   }
 }
 
-__global__ __launch_bounds__(64 * kWavesPerBlock) void contour_emit_kernel(ContourParams p) {
+// five waves per SIMD (at most 96 registers): the pass waits on memory
+__global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(5)))
+void contour_emit_kernel(ContourParams p) {
+  __shared__ EmitLds lds;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int d = (int)(blk / p.bpf);
   const int64_t chunk = (blk % p.bpf) * kWavesPerBlock + wave;
-  if (chunk >= p.nchunk) return;
+  if (chunk >= p.nchunk) return;   // whole wave; the kernel has no barrier
   const float* f = p.fields + (int64_t)d * p.W * p.H;
+  // isovalues 64 at a time, one per lane, with the chunk's output offset of
+  // each; the first 64 are loaded here, in flight with the corner loads, so
+  // that the wave waits once for all of them
+  auto iso_batch = [&](int k0, float& isov, int32_t& off, int64_t& pre) {
+    isov = 0.0f;
+    off = 0;
+    pre = 0;
+    if (k0 + lane < p.n_iso) {
+      const int64_t slot = ((int64_t)d * p.n_iso + k0 + lane) * p.nchunk + chunk;
+      isov = p.iso[d * p.n_iso + k0 + lane];
+      off = p.offsets[slot];
+      pre = p.tile_prefix[slot / kScanTile];
+    }
+  };
+  float isov0;
+  int32_t off0;
+  int64_t pre0;
+  iso_batch(0, isov0, off0, pre0);
   WaveCells w;
   load_wave_cells(p, f, chunk, lane, w);
   const uint64_t below = (1ull << lane) - 1ull;   // lanes before this one
-  // isovalues 64 at a time, one per lane; only those inside the wave's
-  // corner range can have segments here (as in the count pass)
+  int nq = 0;
+  // only the isovalues inside the wave's corner range can have segments
+  // here (as in the count pass)
   float wlo, whi;
   wave_range(w, &wlo, &whi);
   for (int k0 = 0; k0 < p.n_iso; k0 += 64) {
+    float isov = isov0;
+    int32_t offk = off0;
+    int64_t pre = pre0;
+    if (k0 > 0) iso_batch(k0, isov, offk, pre);
+    const int64_t off = pre + offk;
     const bool valid = k0 + lane < p.n_iso;
-    const float isov = valid ? p.iso[d * p.n_iso + k0 + lane] : 0.0f;
     uint64_t act = __ballot(valid && isov > wlo && isov <= whi);
     while (act) {
       const int kk = __builtin_ctzll(act);
       act &= act - 1;
       const float iso = __builtin_bit_cast(
           float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, isov), kk));
-      emit_iso(p, w, d, k0 + kk, iso, chunk, below);
+      const uint64_t ou = (uint64_t)off;
+      const int64_t run = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                                         (int)(uint32_t)(ou >> 32), kk) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ou, kk));
+      queue_iso(p, w, lds, wave, d, k0 + kk, iso, chunk, run, below, lane, nq);
     }
   }
+  if (nq > 0) drain_queue(p, lds, wave, d, chunk, nq, lane);
 }
 
 // Fixed scratch of the allocation-free contour entry point: counts,

@@ -74,3 +74,23 @@ def test_consistent_weight_split(case):
     print(f"max error: consistent split {split[sel].max():.2e}, lo x first term only "
           f"{lo1[sel].max():.2e}")
     assert lo1[sel].max() >= 5 * split[sel].max()
+
+
+def test_attribute_terms_and_lo_weight_are_needed(case):
+    """Cheaper carries, with exact sums, against the built scheme with exact
+    sums: dropping the third BF16 term of the basis x attribute columns
+    (moments keep three), or the lo part of the weight (hi alone on every
+    term, still one weight for all features), each costs more than an order
+    of magnitude of the terms' error, which is then no longer small beside
+    the float32 sums.  Both carries stay."""
+    built, ok, dm = errors(case, accumulate="f64")
+    rhs2, _, _ = errors(case, accumulate="f64", rhs_terms=2)
+    hi, _, _ = errors(case, accumulate="f64", weight="hi")
+    full, _, _ = errors(case)
+    sel = ok & (dm >= 1e-2)
+    e_built, e_rhs2, e_hi, e_full = (x[sel].max() for x in (built, rhs2, hi, full))
+    print(f"exact sums: built {e_built:.2e}, two attribute terms {e_rhs2:.2e}, "
+          f"hi weight only {e_hi:.2e}; full model {e_full:.2e}")
+    assert e_rhs2 >= 10 * e_built
+    assert e_hi >= 5 * e_built
+    assert e_rhs2 >= 0.3 * e_full
