@@ -568,7 +568,8 @@ def fit_step_bench(args, w, prec):
     if prec == "f64":
         peak, kernel, sources = PEAK_F64_MFMA_TFLOPS, "fit_f64_kernel", F64_SOURCES
     else:
-        peak, kernel, sources = PEAK_BF16_MFMA_TFLOPS, "fit_lp_kernel", LP_SOURCES
+        peak, sources = PEAK_BF16_MFMA_TFLOPS, LP_SOURCES
+        kernel = "fit_shape_kernel" if form == 2 else "fit_lp_kernel"
     # counter summaries exist per workload; any other workload reports none
     summary = TRAFFIC_SUMMARIES.get(w.name)
     traffic = profiled_traffic(summary, sources) if summary else None
