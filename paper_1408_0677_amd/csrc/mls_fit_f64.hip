@@ -150,18 +150,17 @@ __device__ __forceinline__ double invpow_weight(double ox, double oy, double alp
   return ldexp((double)exp2f((float)(e - ip)), (int)ip);
 }
 
-// The same weight for alpha = 1 and alpha = 2: (r^2)^-1 and its square from
-// the hardware reciprocal refined by two Newton steps (correct to rounding,
-// where the general form carries float32's 1e-7), about half the vector
-// instructions.  The clamps keep r^2 = 0 finite, as the general form does.
+// The same weight for alpha = 1 and alpha = 2: the float32 reciprocal of
+// r^2 (about 1 ulp of float32, a common relative error of about 1e-7 per
+// pair, as the general form's), squared in float64 for alpha = 2, at about
+// half the vector instructions of the float64 reciprocal with its Newton
+// steps.  Padding points (infinite offset) get 1 / inf = 0; r^2 below
+// float32's smallest normal number is clamped there, so a node on a point
+// gets a large finite weight, as in the general form.
 template <int ALPHA>
 __device__ __forceinline__ double invpow_weight_int(double ox, double oy) {
   const double r2 = ox * ox + oy * oy;
-  if (!(r2 < 1e300)) return 0.0;
-  const double x = fmax(r2, ALPHA == 1 ? 1e-300 : 0x1p-500);
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
+  const double r = (double)__builtin_amdgcn_rcpf(fmaxf((float)r2, 0x1p-126f));
   return ALPHA == 1 ? r : r * r;
 }
 
