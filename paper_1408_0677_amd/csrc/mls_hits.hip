@@ -19,12 +19,10 @@
 namespace mls {
 namespace {
 
-__global__ __launch_bounds__(256) void hit_keys_kernel(const float* pts, int64_t n, double x0,
-                                                       double y0, double dx, double dy, int W,
-                                                       int H, uint32_t* keys, uint32_t* idx) {
+// Node key of a point: the node it lies on exactly, or none.
+__device__ __forceinline__ uint32_t hit_key(const float* pts, int64_t i, double x0, double y0,
+                                            double dx, double dy, int W, int H) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
   const uint32_t none = (uint32_t)W * (uint32_t)H;
   const double px = (double)pts[2 * i], py = (double)pts[2 * i + 1];
   const double fc = rint((px - x0) / dx), fr = rint((py - y0) / dy);
@@ -35,7 +33,15 @@ __global__ __launch_bounds__(256) void hit_keys_kernel(const float* pts, int64_t
     const double ey = py - (y0 + (double)r * dy);
     if (ex * ex + ey * ey == 0.0) key = (uint32_t)r * (uint32_t)W + (uint32_t)c;
   }
-  keys[i] = key;
+  return key;
+}
+
+__global__ __launch_bounds__(256) void hit_keys_kernel(const float* pts, int64_t n, double x0,
+                                                       double y0, double dx, double dy, int W,
+                                                       int H, uint32_t* keys, uint32_t* idx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = hit_key(pts, i, x0, y0, dx, dy, W, H);
   idx[i] = (uint32_t)i;
 }
 
@@ -64,9 +70,94 @@ __global__ __launch_bounds__(256) void hit_mean_kernel(const uint32_t* keys, con
     for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane + k] = __builtin_nanf("");
 }
 
+// Small point sets in one workgroup (one launch instead of a radix sort's
+// dozen): each thread keys four consecutive points, the hitting points are
+// compacted into LDS in index order, and only when there are any are the
+// (node, index) pairs sorted (bitonic, in LDS) and the runs averaged as
+// above.  Sorting by (node, index) orders each node's points by index, as
+// the stable radix sort does, so the sums and results are the same.
+constexpr int kHitSmallThreads = 1024;
+constexpr int kHitSmall = 4 * kHitSmallThreads;   // points of the one-workgroup form
+
+__global__ __launch_bounds__(kHitSmallThreads) void hits_small_kernel(
+    const float* pts, int n, double x0, double y0, double dx, double dy, int W, int H,
+    const float* vals, int D, int64_t plane, float* fields, uint8_t* deg, float* grads) {
+  __shared__ uint64_t pair[kHitSmall];   // node << 32 | point index
+  __shared__ int wsum[kHitSmallThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t none = (uint32_t)W * (uint32_t)H;
+  uint32_t key[4];
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * t + q;
+    key[q] = i < n ? hit_key(pts, i, x0, y0, dx, dy, W, H) : none;
+    cnt += key[q] != none;
+  }
+  // exclusive prefix of the counts over the threads, in index order
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int base = incl - cnt, m = 0;
+#pragma unroll
+  for (int w = 0; w < kHitSmallThreads / 64; ++w) {
+    if (w < wave) base += wsum[w];
+    m += wsum[w];
+  }
+  if (m == 0) return;   // the same in every thread: no barrier is skipped by some only
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (key[q] != none) pair[base++] = ((uint64_t)key[q] << 32) | (uint32_t)(4 * t + q);
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int i = m + t; i < P; i += kHitSmallThreads) pair[i] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < P; i += kHitSmallThreads) {
+        const int ij = i ^ j;
+        if (ij > i) {
+          const uint64_t a = pair[i], b = pair[ij];
+          if (((i & k) == 0) == (a > b)) {
+            pair[i] = b;
+            pair[ij] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = t; i < m; i += kHitSmallThreads) {
+    const uint32_t k = (uint32_t)(pair[i] >> 32);
+    if (i > 0 && (uint32_t)(pair[i - 1] >> 32) == k) continue;
+    int end = i + 1;
+    while (end < m && (uint32_t)(pair[end] >> 32) == k) ++end;
+    const double c = (double)(end - i);
+    for (int d = 0; d < D; ++d) {
+      double sum = 0.0;
+      for (int j = i; j < end; ++j) sum += (double)vals[(int64_t)(uint32_t)pair[j] * D + d];
+      fields[(int64_t)d * plane + k] = (float)(sum / c);
+    }
+    if (deg) deg[k] = 254;
+    if (grads)
+      for (int d = 0; d < 2 * D; ++d) grads[(int64_t)d * plane + k] = __builtin_nanf("");
+  }
+}
+
 }  // namespace
 
 hipError_t launch_hits(const HitArgs& a, hipStream_t s) {
+  if (a.n <= kHitSmall) {
+    hipLaunchKernelGGL(hits_small_kernel, dim3(1), dim3(kHitSmallThreads), 0, s, a.pts, (int)a.n,
+                       a.x0, a.y0, a.dx, a.dy, a.W, a.H, a.vals, a.D, (int64_t)a.W * a.H,
+                       a.fields, a.deg_out, a.grads);
+    return hipGetLastError();
+  }
   const unsigned gb = (unsigned)((a.n + 255) / 256);
   const uint32_t none = (uint32_t)a.W * (uint32_t)a.H;
   hipLaunchKernelGGL(hit_keys_kernel, dim3(gb), dim3(256), 0, s, a.pts, a.n, a.x0, a.y0, a.dx,

@@ -57,12 +57,15 @@ def test_invpow_matches_oracle(torch_dev, oracle, basis, alpha):
     assert st["max_err_pass"] <= TOL
 
 
-def test_exact_hits_take_the_mean(torch_dev, oracle):
+@pytest.mark.parametrize("extra", [200, 5000])
+def test_exact_hits_take_the_mean(torch_dev, oracle, extra):
     """Points placed exactly on grid nodes (pixel centres are dyadic, so the
     float32 point equals the float64 node position): single hits, a double
-    and a triple hit with different values, and near misses 1e-6 away."""
+    and a triple hit with different values, and near misses 1e-6 away, among
+    `extra` random points (211 points in all take the one-workgroup hit
+    pass, 5,011 the radix-sorted one)."""
     from paper_1408_0677_amd import workloads as wl
-    note("case invpow exact hits")
+    note(f"case invpow exact hits, {extra} extra points")
     rng = np.random.default_rng(9)
     # spacings 1/64 and 1/32: node positions are exact in float32 and float64
     grid = wl.pixel_grid(64, 32)
@@ -71,7 +74,7 @@ def test_exact_hits_take_the_mean(torch_dev, oracle):
     hits = [node(3, 5), node(10, 60), node(31, 0), node(0, 63), node(20, 20), node(20, 20),
             node(25, 7), node(25, 7), node(25, 7)]
     near = [(x + 1e-6, y) for x, y in [node(5, 5), node(28, 40)]]
-    pts = np.concatenate([np.array(hits), np.array(near), rng.random((200, 2))])
+    pts = np.concatenate([np.array(hits), np.array(near), rng.random((extra, 2))])
     vals = rng.standard_normal((pts.shape[0], 3))
     F, deg = gpu_fit(torch_dev, pts, vals, grid, basis="linear", weight="invpow", h=0.05)
     of, od, dm = oracle.fit_grid(pts, vals, grid, basis="linear", weight="invpow", h=0.05)
