@@ -824,9 +824,11 @@ __device__ __forceinline__ void point_monomials(const LPParams& p, float x, floa
 }
 
 // Producer, pass 1: tables and the moment monomials (S1 terms, rows
-// s * 16 + j).  Pass 2: tables, the linear basis rows 1, u_x, u_y of the
-// chunk's points (float32, rows 0-2 of `bas`; zero past the reach), and
-// the attribute terms (rows s * kDs + d).
+// s * 16 + j).  Pass 2: tables, the basis values u_x, u_y of the chunk's
+// points (float32, rows 1-2 of `bas`; zero past the reach), and the
+// attribute terms (rows s * kDs + d), zero past the reach: a point beyond
+// every node's reach then adds nothing whatever its effective weight, so
+// the matrix lanes need no reach mask of their own.
 // A thread owns two consecutive points and one eighth of the rows.
 template <int DEG, int NTV, int S1, bool PASS2>
 __device__ __forceinline__ void shape_chunk(const LPParams& p, const float* raw, int kn, int nv,
@@ -847,15 +849,15 @@ __device__ __forceinline__ void shape_chunk(const LPParams& p, const float* raw,
     return;
   }
 #pragma unroll
-  for (int j = 0; j < 3; ++j)   // 1, u_x, u_y (the matrix waves form the rest)
+  for (int j = 1; j < 3; ++j)   // u_x, u_y (the matrix waves form the rest)
     if ((j & 7) == g) {
       bas[j * KSF + k0] = mo0[j];
       bas[j * KSF + k0 + 1] = mo1[j];
     }
   const float* rv = raw + 2 * KT;
   for (int d = g; d < nv; d += 8)
-    emit_terms<kShapeS2>(G + (size_t)d * KSH + k0, (size_t)L::kDs * KSH, rv[d * KT + k0],
-                         rv[d * KT + k0 + 1]);
+    emit_terms<kShapeS2>(G + (size_t)d * KSH + k0, (size_t)L::kDs * KSH,
+                         mo0[0] * rv[d * KT + k0], mo1[0] * rv[d * KT + k0 + 1]);
 }
 
 template <int DEG, int NTV, int S1>
@@ -1050,20 +1052,21 @@ __global__ __launch_bounds__(kThreads) void fit_shape_kernel(LPParams p) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
               const int k = ks + k8 + q + e;
-              // b = (1, u_x, u_y[, u_x^2, u_x u_y, u_y^2]), zero past the
-              // reach: the quadratic terms follow from the linear ones
-              // (Horner), so a point needs three values, not six
-              const float b0 = bs[k], b1 = bs[KSF + k], b2 = bs[2 * KSF + k];
+              // b = (1, u_x, u_y[, u_x^2, u_x u_y, u_y^2]): the quadratic
+              // terms follow from the linear ones (Horner), so a point
+              // needs two values, not five (past the reach its attribute
+              // terms are zero)
+              const float b1 = bs[KSF + k], b2 = bs[2 * KSF + k];
               const float wxq = gx[i * KSF + k];
 #pragma unroll
               for (int t = 0; t < R; ++t) {
                 float sh;
                 if (DEG == 1) {
-                  sh = fmaf(yv[t][2], b2, fmaf(yv[t][1], b1, yv[t][0] * b0));
+                  sh = fmaf(yv[t][2], b2, fmaf(yv[t][1], b1, yv[t][0]));
                 } else {
                   const float s1 = fmaf(yv[t][3], b1, fmaf(yv[t][4], b2, yv[t][1]));
                   const float s2 = fmaf(yv[t][5], b2, yv[t][2]);
-                  sh = fmaf(b1, s1, fmaf(b2, s2, yv[t][0] * b0));
+                  sh = fmaf(b1, s1, fmaf(b2, s2, yv[t][0]));
                 }
                 w[t][e] = (wxq * gy[(wave * R + t) * KSF + k]) * sh;
               }
