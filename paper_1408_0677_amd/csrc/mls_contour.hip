@@ -204,16 +204,34 @@ __device__ __forceinline__ void load_wave_cells(const ContourParams& p, const fl
   }
 }
 
+// One step of a wave reduction: x combined with the value the DPP control
+// moves in (lanes the row mask leaves out combine x with itself).
+template <int CTRL, int ROWS, bool MAX>
+__device__ __forceinline__ float dpp_step(float x) {
+  const int xi = __builtin_bit_cast(int, x);
+  const float y = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(xi, xi, CTRL, ROWS, 0xF, false));
+  return MAX ? fmaxf(x, y) : fminf(x, y);
+}
+
+// Minimum or maximum over the wave, by lane moves within rows (quad
+// permutations, half-row and row mirrors) and the two row broadcasts;
+// lane 63 ends with the whole wave's value.  Short dependent steps of the
+// vector unit, where lane shuffles through LDS wait on its latency.
+template <bool MAX>
+__device__ __forceinline__ float wave_reduce(float x) {
+  x = dpp_step<0xB1, 0xF, MAX>(x);    // quad_perm 1, 0, 3, 2
+  x = dpp_step<0x4E, 0xF, MAX>(x);    // quad_perm 2, 3, 0, 1
+  x = dpp_step<0x141, 0xF, MAX>(x);   // row half mirror
+  x = dpp_step<0x140, 0xF, MAX>(x);   // row mirror
+  x = dpp_step<0x142, 0xA, MAX>(x);   // row broadcast 15 into rows 1 and 3
+  x = dpp_step<0x143, 0xC, MAX>(x);   // row broadcast 31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+
 // The corner range of the whole wave chunk (NaN-free cells only).
 __device__ __forceinline__ void wave_range(const WaveCells& w, float* lo, float* hi) {
-  float a = w.lo, b = w.hi;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a = fminf(a, __shfl_xor(a, o, 64));
-    b = fmaxf(b, __shfl_xor(b, o, 64));
-  }
-  *lo = a;
-  *hi = b;
+  *lo = wave_reduce<false>(w.lo);
+  *hi = wave_reduce<true>(w.hi);
 }
 
 // Segments of one isovalue in a wave chunk: a cell has segments iff
