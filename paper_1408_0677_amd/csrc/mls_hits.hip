@@ -9,7 +9,8 @@
 // coincide with at most one node of a grid with nonzero spacing: the node
 // nearest to it.  Keys (node id, or W*H for none) are radix-sorted with the
 // point index as a stable payload, so every hit node sees its points in
-// index order and sums them in that order.
+// index order and sums them in that order; small point sets do the same in
+// one workgroup (hits_small_kernel below).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
