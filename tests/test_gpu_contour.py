@@ -59,6 +59,31 @@ def test_random_fields_same_input(torch_dev, oracle, shape):
     same_input_check(torch_dev, oracle, f, grid, iso)
 
 
+def test_many_isovalues_without_cases(torch_dev, oracle):
+    """The launch configuration without the case array, where a wave visits
+    only the isovalues inside its corner range, with 150 isovalues per field
+    (three batches of 64, one per lane) on smooth fields, so that a chunk
+    crosses many isovalues and its queue of crossed cells is drained several
+    times: segments and ids equal the oracle's on the same input."""
+    note("case 150 isovalues, no case array")
+    rng = np.random.default_rng(5)
+    W, H, D, n_iso = 203, 151, 2, 150
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    f = np.stack([np.sin(xx / 9.0) * np.cos(yy / 7.0) * 3.0 + 0.01 * rng.standard_normal((H, W)),
+                  (xx - 100.0) ** 2 / 900.0 - (yy - 70.0) ** 2 / 700.0]).astype(np.float32)
+    f[1, 40, 40:60] = np.nan
+    iso = np.stack([np.linspace(-3.0, 3.0, n_iso), np.linspace(-8.0, 12.0, n_iso)]).astype(
+        np.float32)
+    grid = {"x0": -1.0, "y0": 0.5, "dx": 0.01, "dy": 0.02, "width": W, "height": H}
+    segs, ids, cases = gpu_contour(torch_dev, f, grid, iso, want_cases=False)
+    assert cases is None
+    oc, os_, oi = oracle.contour(f, grid, iso, f32=True)
+    note(f"{len(segs)} segments")
+    assert len(segs) > 10000
+    assert np.array_equal(ids, oi)
+    assert np.array_equal(segs, os_.astype(np.float32))
+
+
 def test_every_case_and_saddle(torch_dev, oracle):
     """A field built to contain all 16 cases and both saddle resolutions,
     plus corners equal to the isovalue."""
