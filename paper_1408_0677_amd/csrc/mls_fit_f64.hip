@@ -177,8 +177,21 @@ __device__ __forceinline__ void read4(const double* src, double* dst) {
 // extra solves raise the epilogue's register count, so they are separate
 // instantiations and the plain kernels keep two workgroups per CU), 2 the
 // rigid map of 2-vector values from the linear moments.
-template <int DEG, int NT, int R, int WM, int EPI>
+//
+// Q4 > 0 (one feature tile, F <= 4 Q4 <= 12): the contraction runs on the
+// four-block 4x4x4 FP64 MFMA instead of the 16x16x4 one.  Block b of that
+// instruction takes nodes 4b .. 4b + 3, the same four points k and four
+// feature columns c: lane l holds A (node l % 16, point l / 16) exactly as
+// the 16x16x4 instruction takes it, B (point l / 16, feature l % 4, the
+// same in every block) and the result for node 4 ((l / 4) % 4) + l / 16 and
+// feature l % 4.  Each instruction covers the same 64 node-point pairs over
+// 4 feature columns instead of 16, at about a quarter of the cycles, so the
+// small shapes (Mean MLS F = 3, Affine and Rigid MLS F = 12) issue one to
+// three short instructions where the 16x16x4 one carries 4 to 13 empty
+// columns.
+template <int DEG, int NT, int R, int WM, int EPI, int Q4 = 0>
 __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
+  static_assert(Q4 == 0 || NT == 1, "the 4x4x4 form covers one feature tile");
   constexpr bool INV = WM == WM_INV || WM == WM_INV1 || WM == WM_INV2;
   using L = F64Layout<DEG, NT, R>;
   constexpr int m = DEG == 0 ? 1 : (DEG == 1 ? 3 : 6);
@@ -203,10 +216,14 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
   double* G = lds + L::kG;
 
   doublex4 acc[R][NT];
+  double acc4[R][Q4 > 0 ? Q4 : 1];
 #pragma unroll
-  for (int t = 0; t < R; ++t)
+  for (int t = 0; t < R; ++t) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) acc[t][q] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < (Q4 > 0 ? Q4 : 1); ++q) acc4[t][q] = 0.0;
+  }
 
   const int D = p.D, F = p.F;
   // padding features stay zero for the whole kernel
@@ -389,12 +406,18 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     for (int kg = 0; kg < KT; kg += 16) {
       // four consecutive doubles of a row as two 16-byte reads (rows start
       // on 16-byte boundaries: KS is even and kg + kq a multiple of 4)
-      double ax[4], ay[R][4], bv[NT][4];
+      double ax[4], ay[R][4], bv[Q4 > 0 ? Q4 : NT][4];
       read4(gx + i * KS + kg + kq, ax);
 #pragma unroll
       for (int t = 0; t < R; ++t) read4(gy + (wave * R + t) * KS + kg + kq, ay[t]);
+      if constexpr (Q4 > 0) {
+        // feature 4 q + lane % 4 of the lane's four points
 #pragma unroll
-      for (int q = 0; q < NT; ++q) read4(G + (q * 16 + i) * KS + kg + kq, bv[q]);
+        for (int q = 0; q < Q4; ++q) read4(G + (q * 4 + (lane & 3)) * KS + kg + kq, bv[q]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) read4(G + (q * 16 + i) * KS + kg + kq, bv[q]);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
@@ -403,9 +426,15 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
                            : WM == WM_INV2 ? invpow_weight_int<2>(ax[j], ay[t][j])
                            : INV           ? invpow_weight(ax[j], ay[t][j], p.alpha)
                                            : ax[j] * ay[t][j];
+          if constexpr (Q4 > 0) {
 #pragma unroll
-          for (int q = 0; q < NT; ++q)
-            acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[q][j], acc[t][q], 0, 0, 0);
+            for (int q = 0; q < Q4; ++q)
+              acc4[t][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, bv[q][j], acc4[t][q], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+              acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[q][j], acc[t][q], 0, 0, 0);
+          }
         }
       }
     }
@@ -422,17 +451,29 @@ __global__ __launch_bounds__(kThreads) void fit_f64_kernel(F64Params p) {
     const bool mine = wave >= g && wave < g + kEpiWaves;
     double* epi = lds + (wave - g) * 16 * R * L::kEpiStride;
     if (mine) {
+      if constexpr (Q4 > 0) {
 #pragma unroll
-      for (int t = 0; t < R; ++t)
+        for (int t = 0; t < R; ++t)
 #pragma unroll
-        for (int q = 0; q < NT; ++q)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            // f64 16x16 MFMA result: lane holds row (lane/16 + 4r), column lane%16
-            const int node = t * 16 + (lane >> 4) + 4 * r;
-            const int feat = q * 16 + (lane & 15);
-            epi[node * L::kEpiStride + feat] = acc[t][q][r];
+          for (int q = 0; q < Q4; ++q) {
+            // f64 4x4x4 MFMA result: lane holds node 4 ((lane/4) % 4) + lane/16, feature lane%4
+            const int node = t * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+            const int feat = q * 4 + (lane & 3);
+            epi[node * L::kEpiStride + feat] = acc4[t][q];
           }
+      } else {
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+          for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              // f64 16x16 MFMA result: lane holds row (lane/16 + 4r), column lane%16
+              const int node = t * 16 + (lane >> 4) + 4 * r;
+              const int feat = q * 16 + (lane & 15);
+              epi[node * L::kEpiStride + feat] = acc[t][q][r];
+            }
+      }
     }
     __syncthreads();
     if (mine)
@@ -465,7 +506,7 @@ __device__ void solve_tile_nodes(const F64Params& p, const double* epi, int stri
   }
 }
 
-template <int DEG, int NT, int R, int WM, int EPI>
+template <int DEG, int NT, int R, int WM, int EPI, int Q4 = 0>
 hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   using L = F64Layout<DEG, NT, R>;
   F64Params p = prm;
@@ -473,26 +514,42 @@ hipError_t launch_impl(const F64Params& prm, hipStream_t s) {
   const int tiles_y = (p.H + L::kRows - 1) / L::kRows;
   p.tiles_x = tiles_x;
   const size_t lds_bytes = sizeof(double) * (size_t)L::kDoubles;
-  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, WM, EPI>,
+  hipError_t e = hipFuncSetAttribute((const void*)fit_f64_kernel<DEG, NT, R, WM, EPI, Q4>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
-  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, WM, EPI>), dim3((unsigned)blocks), dim3(kThreads),
-                     lds_bytes, s, p);
+  hipLaunchKernelGGL((fit_f64_kernel<DEG, NT, R, WM, EPI, Q4>), dim3((unsigned)blocks),
+                     dim3(kThreads), lds_bytes, s, p);
   return hipGetLastError();
 }
 
 // R (row strips per wave) trades accumulator registers against the number
 // of Gaussian factors per tile.
-template <int DEG, int NT, int WM>
-hipError_t launch_nt(const F64Params& p, hipStream_t s) {
+template <int DEG, int NT, int WM, int Q4>
+hipError_t launch_epi(const F64Params& p, hipStream_t s) {
   constexpr int R = NT <= 3 ? 4 : (NT <= 6 ? 2 : 1);
   if (p.rigid) {
-    if constexpr (DEG == 1 && NT == 1) return launch_impl<DEG, NT, R, WM, 2>(p, s);
+    if constexpr (DEG == 1 && NT == 1) return launch_impl<DEG, NT, R, WM, 2, Q4>(p, s);
     return hipErrorInvalidValue;
   }
-  return p.grads ? launch_impl<DEG, NT, R, WM, 1>(p, s) : launch_impl<DEG, NT, R, WM, 0>(p, s);
+  return p.grads ? launch_impl<DEG, NT, R, WM, 1, Q4>(p, s)
+                 : launch_impl<DEG, NT, R, WM, 0, Q4>(p, s);
+}
+
+// The inverse-distance weight with at most 12 features (constant basis
+// with D <= 11, linear basis with D <= 2: the timing-table shapes) runs the
+// 4x4x4 form: its vector work per pair is the weight, and the 16x16x4
+// instruction would carry 4 or more empty feature columns.
+template <int DEG, int NT, int WM>
+hipError_t launch_nt(const F64Params& p, hipStream_t s) {
+  constexpr bool INV = WM == WM_INV || WM == WM_INV1 || WM == WM_INV2;
+  if constexpr (INV && NT == 1 && DEG < 2) {
+    if (p.F <= 4) return launch_epi<DEG, NT, WM, 1>(p, s);
+    if (p.F <= 8) return launch_epi<DEG, NT, WM, 2>(p, s);
+    if (p.F <= 12) return launch_epi<DEG, NT, WM, 3>(p, s);
+  }
+  return launch_epi<DEG, NT, WM, 0>(p, s);
 }
 
 template <int DEG, int WM>
