@@ -537,14 +537,12 @@ hipError_t launch_epi(const F64Params& p, hipStream_t s) {
                  : launch_impl<DEG, NT, R, WM, 0, Q4>(p, s);
 }
 
-// The inverse-distance weight with at most 12 features (constant basis
-// with D <= 11, linear basis with D <= 2: the timing-table shapes) runs the
-// 4x4x4 form: its vector work per pair is the weight, and the 16x16x4
-// instruction would carry 4 or more empty feature columns.
+// At most 12 features (constant basis with D <= 11, linear basis with
+// D <= 2, the timing-table shapes among them) run the 4x4x4 form: the
+// 16x16x4 instruction would carry 4 or more empty feature columns.
 template <int DEG, int NT, int WM>
 hipError_t launch_nt(const F64Params& p, hipStream_t s) {
-  constexpr bool INV = WM == WM_INV || WM == WM_INV1 || WM == WM_INV2;
-  if constexpr (INV && NT == 1 && DEG < 2) {
+  if constexpr (NT == 1 && DEG < 2) {
     if (p.F <= 4) return launch_epi<DEG, NT, WM, 1>(p, s);
     if (p.F <= 8) return launch_epi<DEG, NT, WM, 2>(p, s);
     if (p.F <= 12) return launch_epi<DEG, NT, WM, 3>(p, s);
